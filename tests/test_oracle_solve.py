@@ -1,0 +1,214 @@
+"""Pins of the oracle's solvers and of its Schwarz preconditioner.
+
+* dense brute force on 4^4: D assembled column by column, numpy solve;
+* free-field inverse in momentum space;
+* hopping-parameter (Neumann) series at small kappa;
+* RAS against a brute-force block solve built from the (pinned) global hop
+  with every link outside the block zeroed (the Dirichlet cut by definition);
+* the inner/outer solvers reach the unique x = D^-1 b.
+Iteration counts are reported, not pinned (they depend on rounding).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from lattice_ref import coords, free_D_p, gamma5, momenta, parity, plane_wave, rel, spin_apply
+from paper_1612_06556_amd import synth
+
+DIMS4 = (4, 4, 4, 4)
+
+
+@pytest.fixture(scope="module")
+def dense4():
+    kappa, csw = 0.12, 1.0
+    U = synth.su3_field(DIMS4, 1001)
+    o = oracle.Oracle(DIMS4, -1, kappa, csw, U)
+    V = 256
+    N = V * 12
+    D = np.empty((N, N), complex)
+    e = np.zeros(N, complex)
+    for j in range(N):
+        e[:] = 0
+        e[j] = 1
+        D[:, j] = o.D(e.reshape(V, 4, 3)).reshape(N)
+    return o, D
+
+
+def test_dense_gamma5_hermiticity(dense4):
+    o, D = dense4
+    G5 = np.kron(np.eye(256), np.kron(gamma5(), np.eye(3)))
+    assert np.abs(G5 @ D @ G5 - D.conj().T).max() < 1e-14
+
+
+def test_dense_solve_matches_bicgstab(dense4):
+    o, D = dense4
+    b = synth.gaussian_spinor(DIMS4, 2001)
+    xd = np.linalg.solve(D, b.reshape(-1)).reshape(b.shape)
+    x1, i1 = o.bicgstab_full(b, 1e-13, 5000)
+    x2, i2 = o.bicgstab_eo(b, 1e-13, 5000)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert i1["relres"] <= 1e-13 and i2["relres"] <= 1e-13
+    assert rel(x1, xd) < 1e-12
+    assert rel(x2, xd) < 1e-12
+    # the dagger solve: D^dag y = eta equals gamma5 D^-1 gamma5 eta
+    eta = synth.gaussian_spinor(DIMS4, 3001)
+    yd = np.linalg.solve(D.conj().T, eta.reshape(-1)).reshape(eta.shape)
+    g5 = gamma5()
+    y, iy = o.bicgstab_eo(spin_apply(g5, eta), 1e-13, 5000)
+    assert rel(spin_apply(g5, y), yd) < 1e-12
+
+
+def test_dense_schur_and_clover_inverse(dense4):
+    o, D = dense4
+    Tinv = o.clover_inv_matrix()
+    T = o.clover_matrix()
+    for n in (0, 17, 255):
+        blk = D[n * 12:(n + 1) * 12, n * 12:(n + 1) * 12]
+        assert np.abs(blk - T[n]).max() < 1e-15
+        assert np.abs(np.linalg.inv(blk) - Tinv[n]).max() < 1e-13
+
+
+@pytest.mark.parametrize("tbc", [1, -1])
+def test_free_field_inverse(tbc):
+    dims = (4, 4, 6, 8)
+    kappa = 0.124
+    o = oracle.Oracle(dims, tbc, kappa, 1.0, synth.unit_field(dims))
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    p = momenta(dims, (1, 2, 1, 3), tbc)
+    b = plane_wave(dims, p, u)
+    x, info = o.bicgstab_eo(b, 1e-13, 5000)
+    assert info["status"] == 0
+    # closed form D(p)^-1 = [1 - 2k sum cos - 2ik sum gamma sin] / [(1 - 2k sum cos)^2 + 4k^2 sum sin^2]
+    m = 1 - 2 * kappa * np.cos(p).sum()
+    Dp = free_D_p(p, kappa)
+    Dinv = (2 * m * np.eye(4) - Dp) / (m * m + 4 * kappa ** 2 * (np.sin(p) ** 2).sum())
+    assert np.allclose(Dinv @ Dp, np.eye(4), atol=1e-14)
+    assert rel(x, plane_wave(dims, p, Dinv @ u)) < 1e-12
+
+
+def test_neumann_series_small_kappa():
+    """D = 1 - kappa K with K = H + csw C: D^-1 b = sum_n (kappa K)^n b."""
+    dims = (4, 4, 4, 6)
+    kappa, csw = 0.05, 1.0
+    o = oracle.Oracle(dims, -1, kappa, csw, synth.su3_field(dims, 71))
+    b = synth.gaussian_spinor(dims, 72)
+    term = b.copy()
+    acc = b.copy()
+    nb = np.linalg.norm(b)
+    for _ in range(80):
+        term = kappa * (o.hop(term) + csw * o.clover_C(term))
+        acc += term
+        if np.linalg.norm(term) < 1e-15 * nb:
+            break
+    else:
+        pytest.fail("Neumann series did not converge")
+    x, info = o.bicgstab_full(b, 1e-14, 2000)
+    assert rel(x, acc) < 1e-12
+    # and T = 1 - csw kappa C
+    assert rel(o.clover(b), b - csw * kappa * o.clover_C(b)) < 1e-15
+
+
+def _ras_bruteforce(o, dims, U, v, block, overlap, iters):
+    """RAS from the pinned global operator: per block, a copy of the oracle on a
+    gauge field that keeps only the links between locally adjacent sites of the
+    extended block (all other links zero), so its hop is the Dirichlet block
+    hop; minimal residual in numpy; keep the even core sites."""
+    V = len(v)
+    X = coords(dims)
+    even = parity(dims) == 0
+    out = np.zeros_like(v)
+    nbk = [dims[mu] // block[mu] for mu in range(4)]
+    ext = [block[mu] + 2 * overlap for mu in range(4)]
+    for bi in range(int(np.prod(nbk))):
+        rem = bi
+        org = []
+        for mu in range(4):
+            org.append((rem % nbk[mu]) * block[mu])
+            rem //= nbk[mu]
+        # local coordinate of every site in the extended block, -1 if outside
+        loc = np.full((V, 4), -1)
+        inside = np.ones(V, bool)
+        for mu in range(4):
+            a = (X[:, mu] - (org[mu] - overlap)) % dims[mu]
+            inside &= a < ext[mu]
+            loc[:, mu] = a
+        UB = np.zeros_like(U)
+        for mu in range(4):
+            Xp = X.copy(); Xp[:, mu] = (Xp[:, mu] + 1) % dims[mu]
+            npl = Xp[:, 0] + dims[0] * (Xp[:, 1] + dims[1] * (Xp[:, 2] + dims[2] * Xp[:, 3]))
+            keep = inside & inside[npl] & (loc[:, mu] + 1 < ext[mu])
+            UB[keep, mu] = U[keep, mu]
+        oB = oracle.Oracle(dims, o.tbc, o.kappa, o.csw, UB)
+        mask_e = (inside & even)[:, None, None]
+        mask_o = (inside & ~even)[:, None, None]
+
+        def dhat(x):
+            y = o.clover_inv(oB.hop(x) * mask_o) * mask_o
+            return (x - o.kappa ** 2 * o.clover_inv(oB.hop(y) * mask_e)) * mask_e
+
+        r = v * mask_e
+        z = np.zeros_like(v)
+        for _ in range(iters):
+            q = dhat(r)
+            alpha = np.vdot(q, r) / np.vdot(q, q).real
+            z = z + alpha * r
+            r = r - alpha * q
+        core = inside & even
+        for mu in range(4):
+            core &= (loc[:, mu] >= overlap) & (loc[:, mu] < overlap + block[mu])
+        out[core] = z[core]
+    return out
+
+
+@pytest.mark.parametrize("dims,block,overlap", [((4, 4, 4, 4), (2, 2, 2, 2), 1),
+                                                ((8, 4, 4, 4), (4, 2, 2, 2), 1),
+                                                ((4, 4, 4, 8), (2, 2, 2, 4), 0)])
+def test_ras_bruteforce(dims, block, overlap):
+    U = synth.su3_field(dims, 81)
+    o = oracle.Oracle(dims, -1, 0.125, 1.0, U)
+    v = synth.gaussian_spinor(dims, 82)
+    v[parity(dims) == 1] = 0
+    got = o.ras(v, block, overlap, 4)
+    ref = _ras_bruteforce(o, dims, U, v, block, overlap, 4)
+    assert rel(got, ref) < 1e-13
+    assert np.abs(got[parity(dims) == 1]).max() == 0.0
+
+
+def test_ras_rejects_bad_blocks():
+    dims = (4, 4, 4, 4)
+    o = oracle.Oracle(dims, -1, 0.125, 1.0, synth.su3_field(dims, 1))
+    v = synth.gaussian_spinor(dims, 2)
+    with pytest.raises(ValueError):
+        o.ras(v, (4, 4, 4, 4), 1, 4)  # extended block larger than the lattice
+    with pytest.raises(ValueError):
+        o.ras(v, (3, 2, 2, 2), 0, 4)
+
+
+def test_ras_approximates_inverse():
+    """RAS is a preconditioner: ||1 - Dhat M|| well below ||1|| on a smooth field."""
+    dims = (8, 8, 8, 8)
+    o = oracle.Oracle(dims, -1, 0.12, 1.0, synth.su3_field(dims, 91))
+    v = synth.gaussian_spinor(dims, 92)
+    v[parity(dims) == 1] = 0
+    Mv = o.ras(v, (4, 4, 4, 4), 1, 4)
+    assert rel(o.schur(Mv), v) < 0.5
+
+
+@pytest.mark.parametrize("use_ras", [False, True])
+def test_mixed_structure_solvers_reach_the_solution(use_ras):
+    dims = (8, 8, 8, 8)
+    o = oracle.Oracle(dims, -1, 0.12, 1.0, synth.su3_field(dims, 1001))
+    b = synth.gaussian_spinor(dims, 2001)
+    xref, iref = o.bicgstab_eo(b, 1e-13, 5000)
+    assert iref["status"] == 0
+    x, info = o.fbicgstab(b, 1e-10, 50, 1e-3, 200, use_ras, (4, 4, 4, 4), 1, 4)
+    assert info["status"] == 0 and info["relres"] <= 1e-10
+    assert rel(x, xref) < 1e-8
+    # inner solver: relative residual of the Schur system at stol
+    even = parity(dims) == 0
+    bh = o.schur_rhs(b)
+    xi, ii = o.inner_bicgstab(bh / np.linalg.norm(bh), 1e-5, 500, use_ras, (4, 4, 4, 4), 1, 4)
+    assert ii["status"] == 0
+    assert rel(o.schur(xi), bh / np.linalg.norm(bh)) < 1e-5 * 1.0001
+    assert np.abs(xi[~even]).max() == 0.0
