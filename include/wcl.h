@@ -1,0 +1,150 @@
+/*
+ * wcl.h -- C ABI of the MI355X Wilson-Clover library (libwcl.so).
+ *
+ * What it computes (Boku et al., "A performance evaluation of CCS QCD
+ * Benchmark on the COMA system", LATTICE2016):
+ *   - the Wilson-Clover quark matrix D = T - kappa H, whose hopping matrix
+ *     multiplication H is the measured kernel (Sec. 3) and whose inverse on a
+ *     source is the quark propagator (Sec. 1);
+ *   - its solution D x = b by an FP64 flexible BiCGStab preconditioned with a
+ *     single-precision BiCGStab, itself preconditioned by even/odd sites and
+ *     overlapped Restricted Additive Schwarz (Sec. 2); the paper's offload
+ *     entry point takes kappa, a stopping tolerance, an in/out iteration count,
+ *     a read-only source and a written solution (Sec. 2, Fig. "Offloading part
+ *     in the host CPU code") -- the same roles as wcl_solve's arguments here.
+ *
+ * Conventions
+ *   Lattice  dims = {Lx, Ly, Lz, Lt}, every extent even and >= 4; site
+ *            n = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2.
+ *   Gauge    U: complex128 [V][4][3][3]; U[n][mu] is the link from site n in
+ *            direction mu (x, y, z, t), a row-major 3x3 matrix.  The caller
+ *            passes the physical links; the t boundary condition is applied by
+ *            the library as a sign on the hops that cross t = Lt-1 <-> 0.
+ *   Spinor   complex128 [nrhs][V][4][3] ([spin][colour]), chiral gamma basis:
+ *            gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x, y, z),
+ *            gamma_t = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1).
+ *   Operator (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu),
+ *            T = 1 - c_sw kappa sum_{mu<nu} sigma_{mu nu} F_{mu nu},
+ *            sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu], F = (Q - Q^dag)/(8i)
+ *            made traceless, Q the four plaquette leaves; D^dag = g5 D g5.
+ *   Pointers marked _dev are device pointers (HIP) on the context's device;
+ *            every user buffer stays owned by the caller and is not retained
+ *            after the call returns.  All work is ordered on the context's
+ *            stream; calls return once the results are complete on that
+ *            stream (wcl_apply / wcl_apply_op / wcl_set_* do not block the host;
+ *            wcl_solve synchronises for its convergence tests).
+ *   Errors   every call returns WCL_OK (0) or a negative code; the message of
+ *            the last failure on the calling thread is wcl_last_error().
+ */
+#ifndef WCL_H
+#define WCL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wcl_ctx wcl_ctx;
+
+enum {
+    WCL_OK = 0,
+    WCL_EINVAL = -1,      /* bad argument (shape, pointer, option)               */
+    WCL_ENOMEM = -2,      /* device allocation failed                            */
+    WCL_EHIP = -3,        /* a HIP runtime call or kernel launch failed          */
+    WCL_ENOCONV = -4,     /* solver hit its iteration limit; x holds the iterate */
+    WCL_EBREAKDOWN = -5,  /* BiCGStab breakdown (vanishing rho, <r~,v> or omega)  */
+    WCL_ENAN = -6,        /* NaN / Inf in the data                               */
+    WCL_ESTATE = -7       /* apply / solve before wcl_set_gauge + wcl_set_params */
+};
+
+/* Storage precision of links, clover and vectors in wcl_apply / wcl_apply_op. */
+enum { WCL_PREC64 = 64, WCL_PREC32 = 32, WCL_PREC16 = 16 };
+
+/* Create a context for one lattice on the current HIP device.
+ * tile: extents of the internal blocked layout and of the Schwarz cores
+ * (each even and dividing dims[mu]); NULL picks 4^4 when it divides the
+ * lattice, else 2^4.  t_bc = +1 periodic, -1 antiperiodic in time.
+ * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
+ * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL. */
+int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream, wcl_ctx **out);
+int wcl_set_stream(wcl_ctx *ctx, void *hip_stream);
+/* Copy and convert the gauge field (FP64, FP32 and FP16 internal copies). */
+int wcl_set_gauge(wcl_ctx *ctx, const double *U_dev);
+/* Set kappa and c_sw; (re)builds T and T^-1 per site in FP64 (then stored in
+ * FP64, FP32 and FP16).  WCL_ESTATE before wcl_set_gauge; WCL_ENAN if a
+ * clover block is not positive definite. */
+int wcl_set_params(wcl_ctx *ctx, double kappa, double csw);
+
+/* out = D in (dagger = 0) or D^dag in (dagger = 1) on nrhs full-lattice
+ * spinors, computed with links, clover and vectors stored in prec
+ * (64, 32: FP32 storage and arithmetic, 16: FP16 storage, FP32 arithmetic).
+ * in_dev and out_dev must not overlap. */
+int wcl_apply(wcl_ctx *ctx, const double *in_dev, double *out_dev, int nrhs, int dagger, int prec);
+
+/* One step of the hot path on canonical FP64 vectors, for per-step checks:
+ *   WCL_OP_HOP        out = H in                      (both parities)
+ *   WCL_OP_CLOVER     out = T in
+ *   WCL_OP_CLOVER_INV out = T^-1 in
+ *   WCL_OP_SCHUR      out_e = Dhat in_e, out_o = 0, Dhat = 1 - k^2 T_ee^-1 H_eo T_oo^-1 H_oe
+ *   WCL_OP_SCHUR_RHS  out_e = T_ee^-1 (in_e + k H_eo T_oo^-1 in_o), out_o = 0
+ *   WCL_OP_RAS        out_e = M in_e, out_o = 0   (one RAS application; prec 32 or 16,
+ *                     overlap and iterations from the last wcl_set_ras, default 1 and 4)
+ *   WCL_OP_D / WCL_OP_DDAG as wcl_apply.                                   */
+enum { WCL_OP_HOP = 0, WCL_OP_CLOVER = 1, WCL_OP_CLOVER_INV = 2, WCL_OP_SCHUR = 3,
+       WCL_OP_SCHUR_RHS = 4, WCL_OP_RAS = 5, WCL_OP_D = 6, WCL_OP_DDAG = 7 };
+int wcl_apply_op(wcl_ctx *ctx, int op, const double *in_dev, double *out_dev, int nrhs, int prec);
+int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters);
+
+/* Solver options. */
+enum { WCL_OUTER_FBICGSTAB = 0, WCL_OUTER_DC = 1, WCL_OUTER_PLAIN64 = 2 };
+typedef struct {
+    double tol;          /* stop when ||b - D x|| / ||b|| <= tol (true FP64 residual) */
+    int max_outer;       /* outer iterations (PLAIN64: BiCGStab iterations)          */
+    int max_inner;       /* inner iterations per preconditioner call                 */
+    double inner_tol;    /* inner relative residual                                  */
+    int outer;           /* WCL_OUTER_*                                              */
+    int use_ras;         /* RAS preconditioning of the inner solver                  */
+    int ras_overlap;     /* extension of the cores (the tile) on every side          */
+    int ras_iters;       /* minimal-residual steps per block solve                   */
+    int inner_prec;      /* 32: FP32 links/clover; 16: FP16 links/clover (FP32 math) */
+    int use_graph;       /* replay the inner iteration as a captured hipGraph        */
+    int check_every;     /* inner iterations between host convergence checks         */
+} wcl_solve_opts;
+
+typedef struct {
+    int outer_iters;       /* outer iterations (PLAIN64: BiCGStab iterations) */
+    int inner_iters_total; /* inner BiCGStab iterations over all calls        */
+    int status;            /* WCL_OK / WCL_ENOCONV / WCL_EBREAKDOWN / WCL_ENAN */
+    int pad;
+    double true_relres;    /* ||b - D x|| / ||b|| in FP64 at return           */
+    double seconds;        /* wall time of the solve                          */
+} wcl_solve_info;
+
+/* Fill opts with the defaults: tol 1e-10, FBICGSTAB, RAS on (overlap 1,
+ * 4 iterations), inner_tol 1e-2, FP32 inner, 100 outer, 500 inner. */
+void wcl_default_opts(wcl_solve_opts *opts);
+
+/* Solve D x = b for nrhs right-hand sides (one after another, sharing the
+ * context's workspace).  x_dev is written (zero start).  info (nrhs
+ * entries, may be NULL) receives per-rhs results.  Returns the worst status. */
+int wcl_solve(wcl_ctx *ctx, const double *b_dev, double *x_dev, int nrhs, const wcl_solve_opts *opts,
+              wcl_solve_info *info);
+
+/* Gradient of L = Re<eta, D^-1 b> from x = D^-1 b and y = D^-dag eta (both
+ * canonical FP64 device spinors): gU_dev[V][4][3][3] complex128 receives
+ * 2 dL/d conj(U) (PyTorch's convention), *gkappa_host dL/dkappa. */
+int wcl_grad(wcl_ctx *ctx, const double *x_dev, const double *y_dev, double *gU_dev, double *gkappa_host);
+
+/* Time the standalone even/odd hopping kernel H_eo (FP32 or FP16 links):
+ * `reps` launches after 10 warm-ups, rotating over `copies` independent sets
+ * of links and spinors (copies >= 1; more copies defeat the 256 MB Infinity
+ * Cache).  *ms_per_call receives the mean launch time from HIP events. */
+int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
+
+const char *wcl_last_error(void);
+int wcl_destroy(wcl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

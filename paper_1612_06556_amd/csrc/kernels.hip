@@ -1,0 +1,858 @@
+// kernels.hip -- layout conversion, gauge ingest, clover build and inversion,
+// the even/odd hopping kernel with its fused epilogues, precision conversion
+// and the BLAS-1 / reduction kernels of the solvers.
+//
+// The operator (Wilson-Clover, paper Sec. 1 and Sec. 2):
+//   D = T - kappa H,  (H psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu)
+//                                     + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu),
+//   T = 1 - c_sw kappa sum_{mu<nu} sigma_{mu nu} F_{mu nu}  (clover leaves),
+// in the chiral basis; H maps one parity onto the other ("hopping matrix
+// multiplication", the paper's measured kernel, Sec. 3).
+#include "wcl_launch.h"
+
+namespace wcl {
+
+// ---------------------------------------------------------------------------
+// Geometry helpers for the setup kernels (divisions are fine there).
+WCL_D void canon_coords(const Geom &g, int n, int x[4])
+{
+    x[0] = n % g.L[0]; n /= g.L[0];
+    x[1] = n % g.L[1]; n /= g.L[1];
+    x[2] = n % g.L[2];
+    x[3] = n / g.L[2];
+}
+
+WCL_D int coords_to_h(const Geom &g, const int x[4])
+{
+    int blk = 0, lin = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        const int b = x[mu] / g.B[mu];
+        blk += b * g.sb[mu];
+        lin += (x[mu] - b * g.B[mu]) * g.sl[mu];
+    }
+    return blk * g.Hb + (lin >> 1);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical <-> e/o FP64 spinors.
+__global__ void k_pack_spinor(Geom g, const double2 *__restrict__ canon, double2 *__restrict__ eo)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int V = 2 * g.Vh;
+    if (n >= V) return;
+    int x[4];
+    canon_coords(g, n, x);
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const size_t h = coords_to_h(g, x);
+    double2 *dst = eo + (size_t)p * 12 * g.Vh;
+    const double2 *src = canon + (size_t)n * 12;
+#pragma unroll
+    for (int i = 0; i < 12; i++) dst[i * (size_t)g.Vh + h] = src[i];
+}
+
+__global__ void k_unpack_spinor(Geom g, const double2 *__restrict__ eo, double2 *__restrict__ canon)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int V = 2 * g.Vh;
+    if (n >= V) return;
+    int x[4];
+    canon_coords(g, n, x);
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const size_t h = coords_to_h(g, x);
+    const double2 *src = eo + (size_t)p * 12 * g.Vh;
+    double2 *dst = canon + (size_t)n * 12;
+#pragma unroll
+    for (int i = 0; i < 12; i++) dst[i] = src[i * (size_t)g.Vh + h];
+}
+
+hipError_t launch_pack_spinor(const Geom &g, const double *canon, void *eo, hipStream_t st)
+{
+    const int V = 2 * g.Vh;
+    k_pack_spinor<<<(V + 255) / 256, 256, 0, st>>>(g, (const double2 *)canon, (double2 *)eo);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(const Geom &g, const void *eo, double *canon, hipStream_t st)
+{
+    const int V = 2 * g.Vh;
+    k_unpack_spinor<<<(V + 255) / 256, 256, 0, st>>>(g, (const double2 *)eo, (double2 *)canon);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gauge ingest: canonical U[V][4][3][3] complex128 -> internal link fields.
+__global__ void k_ingest_gauge(Geom g, const double2 *__restrict__ canon, void *u64, void *u32, void *u16)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int V = 2 * g.Vh;
+    if (n >= V) return;
+    int x[4];
+    canon_coords(g, n, x);
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const size_t h = coords_to_h(g, x);
+    for (int mu = 0; mu < 4; mu++) {
+        cplx<double> u[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double2 d = canon[((size_t)n * 4 + mu) * 9 + k];
+            u[k] = {d.x, d.y};
+        }
+        if (u64) store_link<double, double>(u64, mu, p, h, g.Vh, u);
+        if (u32) store_link<float, double>(u32, mu, p, h, g.Vh, u);
+        if (u16) store_link<__half, double>(u16, mu, p, h, g.Vh, u);
+    }
+}
+
+hipError_t launch_ingest_gauge(const Geom &g, const double *canon, void *u64, void *u32, void *u16,
+                               hipStream_t st)
+{
+    const int V = 2 * g.Vh;
+    k_ingest_gauge<<<(V + 127) / 128, 128, 0, st>>>(g, (const double2 *)canon, u64, u32, u16);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Clover term.  For each site, F_{mu nu} = (Q - Q^dag)/(8i) made traceless,
+// Q the sum of the four plaquette leaves in the mu-nu plane.  In the chiral
+// basis sum_{mu<nu} sigma_{mu nu} F_{mu nu} is block diagonal:
+//   chirality +: sum_k s_k (x) (E_k - B_k),   chirality -: sum_k s_k (x) (-E_k - B_k)
+// with E_k = F_{k t} and B = (F_yz, F_zx, F_xy), and s_k (x) G written out as
+// [[G_3, G_1 - i G_2], [G_1 + i G_2, -G_3]].
+struct M3 {
+    cplx<double> a[9];
+};
+
+WCL_D M3 m3_mul(const M3 &A, const M3 &B)
+{
+    M3 C;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cplx<double> s = A.a[i * 3] * B.a[j];
+            s = cfma(A.a[i * 3 + 1], B.a[3 + j], s);
+            s = cfma(A.a[i * 3 + 2], B.a[6 + j], s);
+            C.a[i * 3 + j] = s;
+        }
+    return C;
+}
+
+WCL_D M3 m3_dag(const M3 &A)
+{
+    M3 C;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) C.a[i * 3 + j] = {A.a[j * 3 + i].re, -A.a[j * 3 + i].im};
+    return C;
+}
+
+// link U_mu at global coordinates x + d (periodic wrap)
+WCL_D M3 link_at(const Geom &g, const void *u64, const int x[4], const int d[4], int mu)
+{
+    int y[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) y[k] = (x[k] + d[k] + g.L[k]) % g.L[k];
+    const int p = (y[0] + y[1] + y[2] + y[3]) & 1;
+    M3 m;
+    load_link<double, double>(u64, mu, p, coords_to_h(g, y), g.Vh, m.a);
+    return m;
+}
+
+// Traceless F_{mu nu}(x) from the clover leaves.
+WCL_D M3 field_strength(const Geom &g, const void *u64, const int x[4], int mu, int nu)
+{
+    int o[4] = {0, 0, 0, 0};
+    int pm[4] = {0, 0, 0, 0}, pn[4] = {0, 0, 0, 0}, mm[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
+    int mmpn[4] = {0, 0, 0, 0}, mmmn[4] = {0, 0, 0, 0}, pmmn[4] = {0, 0, 0, 0};
+    pm[mu] = 1; pn[nu] = 1; mm[mu] = -1; mn[nu] = -1;
+    mmpn[mu] = -1; mmpn[nu] = 1;
+    mmmn[mu] = -1; mmmn[nu] = -1;
+    pmmn[mu] = 1; pmmn[nu] = -1;
+    // the two links at x are shared by leaves 1 and 4 / 1 and 2
+    const M3 Umu = link_at(g, u64, x, o, mu), Unu = link_at(g, u64, x, o, nu);
+    // leaf 1: x -> x+mu -> x+mu+nu -> x+nu -> x
+    M3 Q = m3_mul(m3_mul(Umu, link_at(g, u64, x, pm, nu)),
+                  m3_mul(m3_dag(link_at(g, u64, x, pn, mu)), m3_dag(Unu)));
+    // leaf 2: x -> x+nu -> x-mu+nu -> x-mu -> x
+    {
+        const M3 a = m3_mul(Unu, m3_dag(link_at(g, u64, x, mmpn, mu)));
+        const M3 b = m3_mul(m3_dag(link_at(g, u64, x, mm, nu)), link_at(g, u64, x, mm, mu));
+        const M3 l = m3_mul(a, b);
+#pragma unroll
+        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
+    }
+    // leaf 3: x -> x-mu -> x-mu-nu -> x-nu -> x
+    {
+        const M3 a = m3_mul(m3_dag(link_at(g, u64, x, mm, mu)), m3_dag(link_at(g, u64, x, mmmn, nu)));
+        const M3 b = m3_mul(link_at(g, u64, x, mmmn, mu), link_at(g, u64, x, mn, nu));
+        const M3 l = m3_mul(a, b);
+#pragma unroll
+        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
+    }
+    // leaf 4: x -> x-nu -> x+mu-nu -> x+mu -> x
+    {
+        const M3 a = m3_mul(m3_dag(link_at(g, u64, x, mn, nu)), link_at(g, u64, x, mn, mu));
+        const M3 b = m3_mul(link_at(g, u64, x, pmmn, nu), m3_dag(Umu));
+        const M3 l = m3_mul(a, b);
+#pragma unroll
+        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
+    }
+    // F = (Q - Q^dag) / (8 i), then remove the trace
+    M3 F;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double wr = Q.a[i * 3 + j].re - Q.a[j * 3 + i].re;
+            const double wi = Q.a[i * 3 + j].im + Q.a[j * 3 + i].im;
+            F.a[i * 3 + j] = {wi * 0.125, -wr * 0.125};
+        }
+    const double tr = (F.a[0].re + F.a[4].re + F.a[8].re) / 3.0;
+    F.a[0].re -= tr; F.a[4].re -= tr; F.a[8].re -= tr;
+    F.a[0].im = F.a[4].im = F.a[8].im = 0.0;
+    return F;
+}
+
+// Inverse of a Hermitian positive definite 6x6 by Cholesky: A = L L^dag,
+// A^-1 = W^dag W with W = L^-1.  Returns false on a non-positive pivot.
+WCL_D bool hpd_inverse6(const cplx<double> A[36], cplx<double> Ai[36])
+{
+    cplx<double> L[36];
+#pragma unroll
+    for (int k = 0; k < 36; k++) L[k] = {0.0, 0.0};
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        double d = A[j * 6 + j].re;
+#pragma unroll
+        for (int k = 0; k < j; k++) d -= L[j * 6 + k].re * L[j * 6 + k].re + L[j * 6 + k].im * L[j * 6 + k].im;
+        if (!(d > 0.0)) { ok = false; d = 1.0; }
+        const double ljj = sqrt(d);
+        L[j * 6 + j] = {ljj, 0.0};
+        const double inv = 1.0 / ljj;
+#pragma unroll
+        for (int i = j + 1; i < 6; i++) {
+            cplx<double> s = A[i * 6 + j];
+#pragma unroll
+            for (int k = 0; k < j; k++) s = s - L[i * 6 + k] * cplx<double>{L[j * 6 + k].re, -L[j * 6 + k].im};
+            L[i * 6 + j] = inv * s;
+        }
+    }
+    // W = L^-1 (lower triangular), forward substitution column by column
+    cplx<double> W[36];
+#pragma unroll
+    for (int k = 0; k < 36; k++) W[k] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        W[j * 6 + j] = {1.0 / L[j * 6 + j].re, 0.0};
+#pragma unroll
+        for (int i = j + 1; i < 6; i++) {
+            cplx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = j; k < i; k++) s = cfma(L[i * 6 + k], W[k * 6 + j], s);
+            W[i * 6 + j] = (-1.0 / L[i * 6 + i].re) * s;
+        }
+    }
+    // Ai = W^dag W
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            cplx<double> s = {0.0, 0.0};
+            const int k0 = i > j ? i : j;
+#pragma unroll
+            for (int k = k0; k < 6; k++) s = cjfma(W[k * 6 + i], W[k * 6 + j], s);
+            Ai[i * 6 + j] = s;
+        }
+    return ok;
+}
+
+WCL_D void pack_block(const cplx<double> A[36], double *out36)
+{
+#pragma unroll
+    for (int i = 0; i < 6; i++) out36[i] = A[i * 6 + i].re;
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i + 1; j < 6; j++) {
+            out36[6 + 2 * k] = A[i * 6 + j].re;
+            out36[7 + 2 * k] = A[i * 6 + j].im;
+            k++;
+        }
+}
+
+__global__ void __launch_bounds__(64) k_clover_build(Geom g, const void *u64, double ck, void *t64, void *ti64,
+                                                     void *t32, void *ti32, void *t16, void *ti16, int *info)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * g.Vh) return;
+    const int p = idx / g.Vh;
+    const int h = idx - p * g.Vh;
+    const Site s = decompose(g, h, p);
+    // planes: E_k = F_{k t}, B_x = F_yz, B_y = -F_xz, B_z = F_xy
+    const M3 E0 = field_strength(g, u64, s.x, 0, 3);
+    const M3 E1 = field_strength(g, u64, s.x, 1, 3);
+    const M3 E2 = field_strength(g, u64, s.x, 2, 3);
+    const M3 Bx = field_strength(g, u64, s.x, 1, 2);
+    const M3 Bym = field_strength(g, u64, s.x, 0, 2);
+    const M3 Bz = field_strength(g, u64, s.x, 0, 1);
+    double packedT[72], packedTi[72];
+    bool ok = true;
+#pragma unroll
+    for (int chi = 0; chi < 2; chi++) {
+        const double se = chi == 0 ? 1.0 : -1.0;
+        // G_k = se * E_k - B_k
+        cplx<double> A[36];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const int k = a * 3 + b;
+                const cplx<double> G1 = se * E0.a[k] - Bx.a[k];
+                const cplx<double> G2 = se * E1.a[k] + Bym.a[k];
+                const cplx<double> G3 = se * E2.a[k] - Bz.a[k];
+                const cplx<double> iG2 = {-G2.im, G2.re};
+                const double id = (a == b) ? 1.0 : 0.0;
+                A[a * 6 + b] = cplx<double>{id, 0.0} - ck * G3;
+                A[(3 + a) * 6 + 3 + b] = cplx<double>{id, 0.0} + ck * G3;
+                A[a * 6 + 3 + b] = -ck * (G1 - iG2);
+                A[(3 + a) * 6 + b] = -ck * (G1 + iG2);
+            }
+        cplx<double> Ai[36];
+        ok = hpd_inverse6(A, Ai) && ok;
+        pack_block(A, packedT + 36 * chi);
+        pack_block(Ai, packedTi + 36 * chi);
+    }
+    if (!ok) atomicAdd(info, 1);
+    if (t64) store_clover<double>(t64, p, h, g.Vh, packedT);
+    if (ti64) store_clover<double>(ti64, p, h, g.Vh, packedTi);
+    if (t32) store_clover<float>(t32, p, h, g.Vh, packedT);
+    if (ti32) store_clover<float>(ti32, p, h, g.Vh, packedTi);
+    if (t16) store_clover<__half>(t16, p, h, g.Vh, packedT);
+    if (ti16) store_clover<__half>(ti16, p, h, g.Vh, packedTi);
+}
+
+hipError_t launch_clover_build(const Geom &g, const void *u64, double ck, void *t64, void *ti64, void *t32,
+                               void *ti32, void *t16, void *ti16, int *info, hipStream_t st)
+{
+    const int n = 2 * g.Vh;
+    k_clover_build<<<(n + 63) / 64, 64, 0, st>>>(g, u64, ck, t64, ti64, t32, ti32, t16, ti16, info);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The hopping kernel.  One thread per output site of parity p; per direction
+// the neighbour spinor is projected to a half spinor (12 flop), rotated by
+// the link or its adjoint (132 flop) and accumulated with the sign pattern of
+// the projector (24 flop): 1320 flop per site over the 8 directions.
+struct HopArgs {
+    Geom g;
+    const void *in;
+    void *out;
+    const void *links;
+    const void *clov;
+    const void *x;
+    double coef;
+    size_t in_stride, out_stride, x_stride;  // bytes between right-hand sides
+    int p;
+    int xcd;
+    const Scalars *sc;
+};
+
+template <typename SL, typename SS, int MU, int SG, typename R>
+WCL_D void hop_dir(const HopArgs &a, const Site &s, size_t h, cplx<R> acc[12], const char *in)
+{
+    const Geom &g = a.g;
+    const size_t Vh = g.Vh;
+    // forward: (1 - SG g_mu) U_mu(x) psi(x + mu)
+    {
+        const int hf = neighbour(g, s, MU, +1);
+        cplx<R> psi[12], hh[6], uh[6], u[9];
+        load_spinor<SS, R>(in, hf, Vh, psi);
+        load_link<SL, R>(a.links, MU, a.p, h, Vh, u);
+        project<MU, -SG, R>(psi, hh);
+        if (MU == 3 && g.tbc < 0 && s.x[3] == g.L[3] - 1) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) hh[k] = -hh[k];
+        }
+        su3_mul(u, hh, uh);
+        accumulate<MU, -SG, R>(acc, uh);
+    }
+    // backward: (1 + SG g_mu) U_mu(x - mu)^dag psi(x - mu)
+    {
+        const int hb = neighbour(g, s, MU, -1);
+        cplx<R> psi[12], hh[6], uh[6], u[9];
+        load_spinor<SS, R>(in, hb, Vh, psi);
+        load_link<SL, R>(a.links, MU, 1 - a.p, hb, Vh, u);
+        project<MU, SG, R>(psi, hh);
+        if (MU == 3 && g.tbc < 0 && s.x[3] == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) hh[k] = -hh[k];
+        }
+        su3_dag_mul(u, hh, uh);
+        accumulate<MU, SG, R>(acc, uh);
+    }
+}
+
+template <typename SL, typename SS, int MODE, bool DAG>
+__global__ void __launch_bounds__(256) k_hop(HopArgs a)
+{
+    using R = typename Real<SL>::T;
+    if (a.sc && a.sc->done) return;
+    const int bid = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h = bid * blockDim.x + threadIdx.x;
+    if (h >= a.g.Vh) return;
+    const size_t Vh = a.g.Vh;
+    const char *in = (const char *)a.in + blockIdx.y * a.in_stride;
+    char *out = (char *)a.out + blockIdx.y * a.out_stride;
+    const Site s = decompose(a.g, h, a.p);
+    constexpr int SG = DAG ? -1 : 1;
+    cplx<R> acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; i++) acc[i] = {R(0), R(0)};
+    hop_dir<SL, SS, 0, SG, R>(a, s, h, acc, in);
+    hop_dir<SL, SS, 1, SG, R>(a, s, h, acc, in);
+    hop_dir<SL, SS, 2, SG, R>(a, s, h, acc, in);
+    hop_dir<SL, SS, 3, SG, R>(a, s, h, acc, in);
+
+    if constexpr (MODE == HOP) {
+        store_spinor<SS, R>(out, h, Vh, acc);
+    } else {
+        R c[72];
+        load_clover<SL, R>(a.clov, a.p, h, Vh, c);
+        cplx<R> o[12];
+        if constexpr (MODE == CLOV_H) {
+            clover_mul(c, acc, o);
+        } else if constexpr (MODE == XPAY) {
+            cplx<R> xv[12], t[12];
+            load_spinor<SS, R>((const char *)a.x + blockIdx.y * a.x_stride, h, Vh, xv);
+            clover_mul(c, acc, t);
+            const R cf = (R)a.coef;
+#pragma unroll
+            for (int i = 0; i < 12; i++) o[i] = {fmar(cf, t[i].re, xv[i].re), fmar(cf, t[i].im, xv[i].im)};
+        } else {
+            cplx<R> xv[12];
+            load_spinor<SS, R>((const char *)a.x + blockIdx.y * a.x_stride, h, Vh, xv);
+            clover_mul(c, xv, o);
+            const R cf = (R)a.coef;
+#pragma unroll
+            for (int i = 0; i < 12; i++) o[i] = {fmar(cf, acc[i].re, o[i].re), fmar(cf, acc[i].im, o[i].im)};
+        }
+        store_spinor<SS, R>(out, h, Vh, o);
+    }
+}
+
+template <typename SL, typename SS, int MODE>
+static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (L.dagger) k_hop<SL, SS, MODE, true><<<grid, block, 0, st>>>(a);
+    else k_hop<SL, SS, MODE, false><<<grid, block, 0, st>>>(a);
+}
+
+template <typename SL, typename SS>
+static void hop_dispatch_mode(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
+{
+    switch (L.mode) {
+    case HOP: hop_dispatch_dag<SL, SS, HOP>(L, a, grid, block, st); break;
+    case CLOV_H: hop_dispatch_dag<SL, SS, CLOV_H>(L, a, grid, block, st); break;
+    case XPAY: hop_dispatch_dag<SL, SS, XPAY>(L, a, grid, block, st); break;
+    default: hop_dispatch_dag<SL, SS, CLOVX>(L, a, grid, block, st); break;
+    }
+}
+
+hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
+{
+    HopArgs a;
+    a.g = *L.g;
+    a.in = L.in;
+    a.out = L.out;
+    a.links = L.links;
+    a.clov = L.clov;
+    a.x = L.x;
+    a.coef = L.coef;
+    a.in_stride = L.in_stride;
+    a.out_stride = L.out_stride;
+    a.x_stride = L.x_stride;
+    a.p = L.p;
+    a.xcd = L.xcd;
+    a.sc = L.sc;
+    const int bs = L.block > 0 ? L.block : 256;
+    if (bs > 256 || bs % 64) return hipErrorInvalidValue;
+    dim3 grid((a.g.Vh + bs - 1) / bs, L.nrhs > 0 ? L.nrhs : 1);
+    dim3 block(bs);
+    if (L.link_prec == P64 && L.spin_prec == P64) hop_dispatch_mode<double, double>(L, a, grid, block, st);
+    else if (L.link_prec == P32 && L.spin_prec == P32) hop_dispatch_mode<float, float>(L, a, grid, block, st);
+    else if (L.link_prec == P16 && L.spin_prec == P32) hop_dispatch_mode<__half, float>(L, a, grid, block, st);
+    else if (L.link_prec == P16 && L.spin_prec == P16) hop_dispatch_mode<__half, __half>(L, a, grid, block, st);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Clover apply: out = A in on one parity (504 flop per site).
+template <typename SL, typename SS>
+__global__ void __launch_bounds__(256) k_clover(Geom g, int p, const void *clov, const void *in, void *out)
+{
+    using R = typename Real<SL>::T;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= g.Vh) return;
+    R c[72];
+    cplx<R> v[12], o[12];
+    load_clover<SL, R>(clov, p, h, g.Vh, c);
+    load_spinor<SS, R>(in, h, g.Vh, v);
+    clover_mul(c, v, o);
+    store_spinor<SS, R>(out, h, g.Vh, o);
+}
+
+hipError_t launch_clover(const Geom &g, int lp, int sp, int p, const void *clov, const void *in, void *out,
+                         hipStream_t st)
+{
+    dim3 grid((g.Vh + 255) / 256), block(256);
+    if (lp == P64 && sp == P64) k_clover<double, double><<<grid, block, 0, st>>>(g, p, clov, in, out);
+    else if (lp == P32 && sp == P32) k_clover<float, float><<<grid, block, 0, st>>>(g, p, clov, in, out);
+    else if (lp == P16 && sp == P32) k_clover<__half, float><<<grid, block, 0, st>>>(g, p, clov, in, out);
+    else if (lp == P16 && sp == P16) k_clover<__half, __half><<<grid, block, 0, st>>>(g, p, clov, in, out);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Precision conversion of spinor sections (each section Vh sites).
+template <typename SI, typename SO>
+__global__ void k_convert(size_t nsites, size_t Vi, size_t Vo, const char *in, char *out, const double *sdev,
+                          int mode, double shost)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsites) return;
+    double sc = shost;
+    if (mode == 1) sc = (*sdev > 0.0) ? shost / sqrt(*sdev) : 0.0;
+    else if (mode == 2) sc = shost * sqrt(*sdev);
+    const size_t sec = i / Vi, h = i - sec * Vi;
+    cplx<double> v[12];
+    load_spinor<SI, double>(in + sec * spinor_bytes(sizeof(SI), Vi), h, Vi, v);
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = sc * v[k];
+    store_spinor<SO, double>(out + sec * spinor_bytes(sizeof(SO), Vo), h, Vo, v);
+}
+
+hipError_t launch_convert(int ip, int op, size_t nsites, size_t Vi, size_t Vo, const void *in, void *out,
+                          const double *sdev, int mode, double shost, hipStream_t st)
+{
+    dim3 grid((unsigned)((nsites + 255) / 256)), block(256);
+    const char *i = (const char *)in;
+    char *o = (char *)out;
+#define WCL_CONV(A, B) k_convert<A, B><<<grid, block, 0, st>>>(nsites, Vi, Vo, i, o, sdev, mode, shost)
+    if (ip == P64 && op == P32) WCL_CONV(double, float);
+    else if (ip == P32 && op == P64) WCL_CONV(float, double);
+    else if (ip == P64 && op == P16) WCL_CONV(double, __half);
+    else if (ip == P16 && op == P64) WCL_CONV(__half, double);
+    else if (ip == P64 && op == P64) WCL_CONV(double, double);
+    else if (ip == P32 && op == P32) WCL_CONV(float, float);
+    else if (ip == P32 && op == P16) WCL_CONV(float, __half);
+    else if (ip == P16 && op == P32) WCL_CONV(__half, float);
+    else return hipErrorInvalidValue;
+#undef WCL_CONV
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: wavefront butterfly (DPP / ds_swizzle through __shfl_xor), then
+// one value per wave through LDS.
+WCL_D double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NV>
+WCL_D void block_sum(double v[NV], double *lds /* [NV][16] */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) lds[k * 16 + wid] = v[k];
+    }
+    __syncthreads();
+    if (wid == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            double t = lane < nw ? lds[k * 16 + lane] : 0.0;
+            v[k] = wave_sum(t);
+        }
+    }
+}
+
+template <typename T>
+struct CT;
+template <> struct CT<double> { using V = double2; };
+template <> struct CT<float> { using V = float2; };
+
+// partials[(2*k + {0,1}) * RED_BLOCKS + block] = (Re, Im) of sum conj(a_k) b_k
+template <typename T, int NP>
+__global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, const typename CT<T>::V *a0, const typename CT<T>::V *b0,
+                                                      const typename CT<T>::V *a1, const typename CT<T>::V *b1,
+                                                      const typename CT<T>::V *a2, const typename CT<T>::V *b2,
+                                                      double *partials, const Scalars *sc)
+{
+    if (sc && sc->done) return;
+    __shared__ double lds[2 * NP * 16];
+    double v[2 * NP];
+#pragma unroll
+    for (int k = 0; k < 2 * NP; k++) v[k] = 0.0;
+    const typename CT<T>::V *A[3] = {a0, a1, a2}, *B[3] = {b0, b1, b2};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const auto x = A[k][i], y = B[k][i];
+            v[2 * k] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+            v[2 * k + 1] += (double)x.x * (double)y.y - (double)x.y * (double)y.x;
+        }
+    }
+    block_sum<2 * NP>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 2 * NP; k++) partials[k * RED_BLOCKS + blockIdx.x] = v[k];
+    }
+}
+
+hipError_t launch_dots(int prec, size_t n, int np, const void *const *a, const void *const *b, double *partials,
+                       const Scalars *sc, hipStream_t st)
+{
+    const void *A[3] = {a[0], np > 1 ? a[1] : a[0], np > 2 ? a[2] : a[0]};
+    const void *B[3] = {b[0], np > 1 ? b[1] : b[0], np > 2 ? b[2] : b[0]};
+    dim3 grid(RED_BLOCKS), block(RED_THREADS);
+#define WCL_DOTS(T, NP)                                                                                   \
+    k_dots<T, NP><<<grid, block, 0, st>>>(n, (const CT<T>::V *)A[0], (const CT<T>::V *)B[0],              \
+                                          (const CT<T>::V *)A[1], (const CT<T>::V *)B[1],                 \
+                                          (const CT<T>::V *)A[2], (const CT<T>::V *)B[2], partials, sc)
+    if (prec == P64) {
+        if (np == 1) WCL_DOTS(double, 1);
+        else if (np == 2) WCL_DOTS(double, 2);
+        else WCL_DOTS(double, 3);
+    } else if (prec == P32) {
+        if (np == 1) WCL_DOTS(float, 1);
+        else if (np == 2) WCL_DOTS(float, 2);
+        else WCL_DOTS(float, 3);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef WCL_DOTS
+    return hipGetLastError();
+}
+
+WCL_D void cdiv(const double a[2], const double b[2], double o[2])
+{
+    const double d = b[0] * b[0] + b[1] * b[1];
+    o[0] = (a[0] * b[0] + a[1] * b[1]) / d;
+    o[1] = (a[1] * b[0] - a[0] * b[1]) / d;
+}
+
+__global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const double *partials, Scalars *sc)
+{
+    if (sc->done && (step == BICG_ALPHA || step == BICG_OMEGA || step == BICG_RHO)) return;
+    __shared__ double lds[6 * 16];
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double t = 0.0;
+        if (k < nterms)
+            for (int j = threadIdx.x; j < RED_BLOCKS; j += blockDim.x) t += partials[k * RED_BLOCKS + j];
+        v[k] = t;
+    }
+    block_sum<6>(v, lds);
+    if (threadIdx.x != 0) return;
+    switch (step) {
+    case BICG_INIT_RHO:
+        // pairs (rt, r), (r, r)
+        sc->rho[0] = v[0]; sc->rho[1] = v[1];
+        sc->r2 = v[2];
+        sc->b2 = v[2];
+        sc->rho_old[0] = 1.0; sc->rho_old[1] = 0.0;
+        sc->alpha[0] = 1.0; sc->alpha[1] = 0.0;
+        sc->omega[0] = 1.0; sc->omega[1] = 0.0;
+        sc->iter = 0;
+        sc->done = (v[2] == 0.0) ? 1 : 0;
+        break;
+    case BICG_ALPHA: {
+        const double d[2] = {v[0], v[1]};
+        if (d[0] == 0.0 && d[1] == 0.0) { sc->done = 2; break; }
+        cdiv(sc->rho, d, sc->alpha);
+        break;
+    }
+    case BICG_OMEGA: {
+        // pairs (t, s), (t, t)
+        const double tt = v[2];
+        if (tt == 0.0) { sc->omega[0] = 0.0; sc->omega[1] = 0.0; }
+        else { sc->omega[0] = v[0] / tt; sc->omega[1] = v[1] / tt; }
+        break;
+    }
+    case BICG_RHO:
+        sc->rho_old[0] = sc->rho[0]; sc->rho_old[1] = sc->rho[1];
+        sc->rho[0] = v[0]; sc->rho[1] = v[1];
+        sc->r2 = v[2];
+        sc->iter += 1;
+        if (!(v[2] <= sc->stop2 * sc->b2) && !(v[2] >= 0.0)) sc->done = 2;     // NaN
+        else if (v[2] <= sc->stop2 * sc->b2) sc->done = 1;
+        else if ((sc->omega[0] == 0.0 && sc->omega[1] == 0.0) || (v[0] == 0.0 && v[1] == 0.0)) sc->done = 2;
+        break;
+    case NORM_ONLY:
+        sc->t[0] = v[0];
+        break;
+    default:
+        break;
+    }
+}
+
+hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st)
+{
+    k_finalize<<<1, 256, 0, st>>>(step, nterms, partials, sc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab vector updates (complex scalars from the device).
+template <typename T>
+WCL_D typename CT<T>::V cv(double re, double im) { return {(T)re, (T)im}; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bicg_p(size_t n, const typename CT<T>::V *r, typename CT<T>::V *p,
+                                               const typename CT<T>::V *v, const Scalars *sc)
+{
+    if (sc->done) return;
+    // beta = (rho / rho_old) (alpha / omega)
+    double q1[2], q2[2], beta[2];
+    cdiv(sc->rho, sc->rho_old, q1);
+    cdiv(sc->alpha, sc->omega, q2);
+    beta[0] = q1[0] * q2[0] - q1[1] * q2[1];
+    beta[1] = q1[0] * q2[1] + q1[1] * q2[0];
+    const T br = (T)beta[0], bi = (T)beta[1], wr = (T)sc->omega[0], wi = (T)sc->omega[1];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const auto pv = p[i], vv = v[i], rv = r[i];
+        // d = p - omega v
+        const T dr = pv.x - (wr * vv.x - wi * vv.y);
+        const T di = pv.y - (wr * vv.y + wi * vv.x);
+        p[i] = {rv.x + br * dr - bi * di, rv.y + br * di + bi * dr};
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bicg_s(size_t n, const typename CT<T>::V *r, const typename CT<T>::V *v,
+                                               typename CT<T>::V *s, const Scalars *sc)
+{
+    if (sc->done) return;
+    const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const auto rv = r[i], vv = v[i];
+        s[i] = {rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x)};
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bicg_xr(size_t n, typename CT<T>::V *x, const typename CT<T>::V *ph,
+                                                const typename CT<T>::V *sh, typename CT<T>::V *r,
+                                                const typename CT<T>::V *s, const typename CT<T>::V *t,
+                                                const Scalars *sc)
+{
+    if (sc->done) return;
+    const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1], wr = (T)sc->omega[0], wi = (T)sc->omega[1];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const auto xv = x[i], pv = ph[i], sv = sh[i], s2 = s[i], tv = t[i];
+        x[i] = {xv.x + (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y),
+                xv.y + (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x)};
+        r[i] = {s2.x - (wr * tv.x - wi * tv.y), s2.y - (wr * tv.y + wi * tv.x)};
+    }
+}
+
+static dim3 blas_grid(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
+                         hipStream_t st)
+{
+    if (prec == P64)
+        k_bicg_p<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)r, (double2 *)p, (const double2 *)v, sc);
+    else
+        k_bicg_p<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)r, (float2 *)p, (const float2 *)v, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void *s, const Scalars *sc,
+                         hipStream_t st)
+{
+    if (prec == P64)
+        k_bicg_s<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)r, (const double2 *)v, (double2 *)s, sc);
+    else
+        k_bicg_s<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)r, (const float2 *)v, (float2 *)s, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r, const void *s,
+                          const void *t, const Scalars *sc, hipStream_t st)
+{
+    if (prec == P64)
+        k_bicg_xr<double><<<blas_grid(n), 256, 0, st>>>(n, (double2 *)x, (const double2 *)ph, (const double2 *)sh,
+                                                        (double2 *)r, (const double2 *)s, (const double2 *)t, sc);
+    else
+        k_bicg_xr<float><<<blas_grid(n), 256, 0, st>>>(n, (float2 *)x, (const float2 *)ph, (const float2 *)sh,
+                                                       (float2 *)r, (const float2 *)s, (const float2 *)t, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_axpby(size_t n, double ar, double ai, const typename CT<T>::V *x, double br,
+                                              double bi, typename CT<T>::V *y)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const auto xv = x[i], yv = y[i];
+        y[i] = {(T)(ar * xv.x - ai * xv.y + br * yv.x - bi * yv.y), (T)(ar * xv.y + ai * xv.x + br * yv.y + bi * yv.x)};
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy(size_t n, const typename CT<T>::V *x, typename CT<T>::V *y)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero(size_t n, typename CT<T>::V *y)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = {(T)0, (T)0};
+}
+
+hipError_t launch_axpby(int prec, size_t n, double2 a, const void *x, double2 b, void *y, hipStream_t st)
+{
+    if (prec == P64)
+        k_axpby<double><<<blas_grid(n), 256, 0, st>>>(n, a.x, a.y, (const double2 *)x, b.x, b.y, (double2 *)y);
+    else
+        k_axpby<float><<<blas_grid(n), 256, 0, st>>>(n, a.x, a.y, (const float2 *)x, b.x, b.y, (float2 *)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int prec, size_t n, const void *x, void *y, hipStream_t st)
+{
+    if (prec == P64) k_copy<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)x, (double2 *)y);
+    else k_copy<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)x, (float2 *)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(int prec, size_t n, void *y, hipStream_t st)
+{
+    if (prec == P64) k_zero<double><<<blas_grid(n), 256, 0, st>>>(n, (double2 *)y);
+    else k_zero<float><<<blas_grid(n), 256, 0, st>>>(n, (float2 *)y);
+    return hipGetLastError();
+}
+
+}  // namespace wcl

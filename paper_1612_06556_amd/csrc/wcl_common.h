@@ -1,0 +1,494 @@
+// wcl_common.h -- shared definitions of the MI355X Wilson-Clover library:
+// lattice geometry of the blocked even/odd layout, storage formats, complex
+// arithmetic and the gamma-projection tables of the chiral basis.
+//
+// Layout of every internal field ("blocked even/odd"): the lattice is tiled by
+// hypercubes of extent tile[mu] (even, dividing L[mu]); these tiles are also
+// the cores of the Schwarz blocks.  A site of parity p (= (x+y+z+t) mod 2) has
+// half index h = tile_id * Hb + l/2, where tile_id is the lexicographic index
+// of its tile, l the lexicographic index inside the tile and Hb the number of
+// sites of one parity per tile.  Consecutive threads therefore read
+// consecutive sites of one tile, and a Schwarz core is one contiguous range.
+//
+// Storage (structure of arrays, the site index innermost, one parity):
+//   spinor   double : double2 [12][Vh]      complex component i = spin*3+colour
+//            float  : float4  [6][Vh]       components (2k, 2k+1)
+//            half   : uint4   [3][Vh]       components (4k .. 4k+3) as 8 halves
+//   links    double : double2 [4 mu][2 p][9][Vh]   row-major 3x3
+//            float  : float4  [4][2][4][Vh] (reals 0..15) + float2 [4][2][Vh]
+//            half   : uint4   [4][2][2][Vh] (reals 0..15) + uint32 [4][2][Vh]
+//   clover   double : double2 [2 p][36][Vh]
+//            float  : float4  [2 p][18][Vh]
+//            half   : uint4   [2 p][9][Vh]
+//   A clover site holds two Hermitian 6x6 chirality blocks (spins 0,1 and
+//   2,3), each packed as 6 real diagonal entries followed by the 15 complex
+//   entries above the diagonal in row-major order: 36 reals per block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define WCL_HD __host__ __device__ __forceinline__
+#define WCL_D __device__ __forceinline__
+
+namespace wcl {
+
+// ---------------------------------------------------------------------------
+// Division by an invariant integer (Granlund & Montgomery 1994): for
+// n < 2^31, q = (umulhi(n, m) + n) >> s with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) s++;
+    f.s = s;
+    f.m = (uint32_t)((((1ull << s) - d) << 32) / d + 1);
+    return f;
+}
+
+WCL_D uint32_t fdiv(uint32_t n, const FastDiv &f) { return (__umulhi(n, f.m) + n) >> f.s; }
+
+inline uint32_t fdiv_host(uint32_t n, const FastDiv &f)
+{
+    return (uint32_t)((((uint64_t)n * f.m) >> 32) + n) >> f.s;
+}
+
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4];        // lattice extents
+    int B[4];        // tile extents (even, divide L)
+    int NB[4];       // tiles per direction
+    int Vh;          // sites per parity
+    int Hb;          // sites per parity per tile
+    int tbc;         // +1 periodic, -1 antiperiodic in t (fermion hops)
+    int sl[4];       // strides of the in-tile lexicographic index
+    int sb[4];       // strides of the tile index
+    FastDiv dHb, dNB0, dNB1, dNB2, dBh0, dB1, dB2;
+};
+
+// Coordinates of the site with half index h and parity p.
+struct Site {
+    int x[4];   // global coordinates
+    int l[4];   // coordinates inside the tile
+    int b[4];   // tile coordinates
+    int blk;    // tile index
+    int lin;    // lexicographic index inside the tile
+};
+
+WCL_D Site decompose(const Geom &g, int h, int p)
+{
+    Site s;
+    const uint32_t blk = fdiv((uint32_t)h, g.dHb);
+    const uint32_t l2 = (uint32_t)h - blk * (uint32_t)g.Hb;
+    uint32_t r = blk, q;
+    q = fdiv(r, g.dNB0); const int b0 = (int)(r - q * g.NB[0]); r = q;
+    q = fdiv(r, g.dNB1); const int b1 = (int)(r - q * g.NB[1]); r = q;
+    q = fdiv(r, g.dNB2); const int b2 = (int)(r - q * g.NB[2]); const int b3 = (int)q;
+    r = l2;
+    q = fdiv(r, g.dBh0); const int lxh = (int)(r - q * (g.B[0] >> 1)); r = q;
+    q = fdiv(r, g.dB1); const int l1 = (int)(r - q * g.B[1]); r = q;
+    q = fdiv(r, g.dB2); const int l2c = (int)(r - q * g.B[2]); const int l3 = (int)q;
+    const int l0 = 2 * lxh + ((p + l1 + l2c + l3) & 1);
+    s.l[0] = l0; s.l[1] = l1; s.l[2] = l2c; s.l[3] = l3;
+    s.b[0] = b0; s.b[1] = b1; s.b[2] = b2; s.b[3] = b3;
+    s.x[0] = b0 * g.B[0] + l0;
+    s.x[1] = b1 * g.B[1] + l1;
+    s.x[2] = b2 * g.B[2] + l2c;
+    s.x[3] = b3 * g.B[3] + l3;
+    s.blk = (int)blk;
+    s.lin = l0 + g.B[0] * (l1 + g.B[1] * (l2c + g.B[2] * l3));
+    return s;
+}
+
+// Half index of the neighbour of s in direction mu (dir = +1 / -1); the tile
+// index changes only when the step leaves the tile (wrapping the lattice).
+WCL_D int neighbour(const Geom &g, const Site &s, int mu, int dir)
+{
+    int lin = s.lin, blk = s.blk;
+    const int lc = s.l[mu] + dir;
+    const int bc = s.b[mu];
+    if (lc >= 0 && lc < g.B[mu]) {
+        lin += dir * g.sl[mu];
+    } else {
+        lin -= dir * (g.B[mu] - 1) * g.sl[mu];
+        const int nbc = bc + dir;
+        if (nbc < 0) blk += (g.NB[mu] - 1) * g.sb[mu];
+        else if (nbc >= g.NB[mu]) blk -= (g.NB[mu] - 1) * g.sb[mu];
+        else blk += dir * g.sb[mu];
+    }
+    return blk * g.Hb + (lin >> 1);
+}
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic.
+template <typename R>
+struct cplx {
+    R re, im;
+};
+
+template <typename R> WCL_HD cplx<R> cmk(R a, R b) { return cplx<R>{a, b}; }
+template <typename R> WCL_HD cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> WCL_HD cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> WCL_HD cplx<R> operator-(cplx<R> a) { return {-a.re, -a.im}; }
+template <typename R> WCL_HD cplx<R> operator*(cplx<R> a, cplx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> WCL_HD cplx<R> operator*(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> WCL_HD cplx<R> conjm(cplx<R> a, cplx<R> b)  // conj(a) * b
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+WCL_HD float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+WCL_HD double fmar(double a, double b, double c) { return fma(a, b, c); }
+template <typename R> WCL_HD cplx<R> cfma(cplx<R> a, cplx<R> b, cplx<R> c)  // a*b + c
+{
+    return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
+}
+template <typename R> WCL_HD cplx<R> cjfma(cplx<R> a, cplx<R> b, cplx<R> c)  // conj(a)*b + c
+{
+    return {fmar(a.re, b.re, fmar(a.im, b.im, c.re)), fmar(a.re, b.im, fmar(-a.im, b.re, c.im))};
+}
+
+// Multiplication by the unit i^code, code = 0:+1, 1:+i, 2:-1, 3:-i.
+template <int CODE, typename R> WCL_D cplx<R> mul_unit(cplx<R> a)
+{
+    if constexpr ((CODE & 3) == 0) return a;
+    else if constexpr ((CODE & 3) == 1) return {-a.im, a.re};
+    else if constexpr ((CODE & 3) == 2) return {-a.re, -a.im};
+    else return {a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// Chiral basis: gamma_mu = [[0, G_mu], [G_mu^dag, 0]] with G_x = -i s1,
+// G_y = -i s2, G_z = -i s3, G_t = 1.  Every row of G and G^dag has a single
+// non-zero entry, a unit i^code:  (G psi_lo)_r = i^GC[mu][r] psi_lo[GCOL[mu][r]].
+__host__ __device__ constexpr int gcol(int mu, int r) { return (mu <= 1) ? 1 - r : r; }
+__host__ __device__ constexpr int gcode(int mu, int r)
+{
+    return mu == 0 ? 3 : mu == 1 ? (r == 0 ? 2 : 0) : mu == 2 ? (r == 0 ? 3 : 1) : 0;
+}
+__host__ __device__ constexpr int gdcode(int mu, int r)
+{
+    return mu == 0 ? 1 : mu == 1 ? (r == 0 ? 0 : 2) : mu == 2 ? (r == 0 ? 1 : 3) : 0;
+}
+
+// Half spinor for the projector (1 + S gamma_mu):  h = psi_up + S G psi_lo.
+template <int MU, int S, typename R>
+WCL_D void project(const cplx<R> psi[12], cplx<R> h[6])
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        const int c0 = gcol(MU, r);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const cplx<R> lo = psi[(2 + c0) * 3 + c];
+            cplx<R> t;
+            if (r == 0) t = mul_unit<gcode(MU, 0) + (S < 0 ? 2 : 0)>(lo);
+            else t = mul_unit<gcode(MU, 1) + (S < 0 ? 2 : 0)>(lo);
+            h[r * 3 + c] = psi[r * 3 + c] + t;
+        }
+    }
+}
+
+// acc += (1 + S gamma_mu) applied to a projected, colour-rotated half spinor:
+// upper += uh, lower += S G^dag uh.
+template <int MU, int S, typename R>
+WCL_D void accumulate(cplx<R> acc[12], const cplx<R> uh[6])
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        const int c0 = gcol(MU, r);  // G^dag has the same column pattern as G
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[r * 3 + c] = acc[r * 3 + c] + uh[r * 3 + c];
+            cplx<R> t;
+            if (r == 0) t = mul_unit<gdcode(MU, 0) + (S < 0 ? 2 : 0)>(uh[c0 * 3 + c]);
+            else t = mul_unit<gdcode(MU, 1) + (S < 0 ? 2 : 0)>(uh[c0 * 3 + c]);
+            acc[(2 + r) * 3 + c] = acc[(2 + r) * 3 + c] + t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats.
+template <typename S> struct Real { using T = float; };
+template <> struct Real<double> { using T = double; };
+
+WCL_D float2 h2f2(uint32_t u)
+{
+    __half2 h = *reinterpret_cast<__half2 *>(&u);
+    return __half22float2(h);
+}
+WCL_D uint32_t f22h(float a, float b)
+{
+    __half2 h = __floats2half2_rn(a, b);
+    return *reinterpret_cast<uint32_t *>(&h);
+}
+
+template <typename S, typename R>
+WCL_D void load_spinor(const void *base, size_t h, size_t Vh, cplx<R> v[12])
+{
+    if constexpr (sizeof(S) == 8) {
+        const double2 *p = (const double2 *)base;
+#pragma unroll
+        for (int i = 0; i < 12; i++) {
+            const double2 d = p[i * Vh + h];
+            v[i] = {(R)d.x, (R)d.y};
+        }
+    } else if constexpr (sizeof(S) == 4) {
+        const float4 *p = (const float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const float4 f = p[k * Vh + h];
+            v[2 * k] = {(R)f.x, (R)f.y};
+            v[2 * k + 1] = {(R)f.z, (R)f.w};
+        }
+    } else {
+        const uint4 *p = (const uint4 *)base;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 u = p[k * Vh + h];
+            float2 a = h2f2(u.x), b = h2f2(u.y), c = h2f2(u.z), d = h2f2(u.w);
+            v[4 * k + 0] = {(R)a.x, (R)a.y};
+            v[4 * k + 1] = {(R)b.x, (R)b.y};
+            v[4 * k + 2] = {(R)c.x, (R)c.y};
+            v[4 * k + 3] = {(R)d.x, (R)d.y};
+        }
+    }
+}
+
+template <typename S, typename R>
+WCL_D void store_spinor(void *base, size_t h, size_t Vh, const cplx<R> v[12])
+{
+    if constexpr (sizeof(S) == 8) {
+        double2 *p = (double2 *)base;
+#pragma unroll
+        for (int i = 0; i < 12; i++) p[i * Vh + h] = make_double2((double)v[i].re, (double)v[i].im);
+    } else if constexpr (sizeof(S) == 4) {
+        float4 *p = (float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            p[k * Vh + h] = make_float4((float)v[2 * k].re, (float)v[2 * k].im, (float)v[2 * k + 1].re,
+                                        (float)v[2 * k + 1].im);
+    } else {
+        uint4 *p = (uint4 *)base;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 u;
+            u.x = f22h((float)v[4 * k].re, (float)v[4 * k].im);
+            u.y = f22h((float)v[4 * k + 1].re, (float)v[4 * k + 1].im);
+            u.z = f22h((float)v[4 * k + 2].re, (float)v[4 * k + 2].im);
+            u.w = f22h((float)v[4 * k + 3].re, (float)v[4 * k + 3].im);
+            p[k * Vh + h] = u;
+        }
+    }
+}
+
+// Link U_mu at (parity p, half index h): 9 complex, row-major.
+template <typename S, typename R>
+WCL_D void load_link(const void *base, int mu, int p, size_t h, size_t Vh, cplx<R> u[9])
+{
+    const size_t mp = (size_t)(mu * 2 + p);
+    if constexpr (sizeof(S) == 8) {
+        const double2 *q = (const double2 *)base + mp * 9 * Vh;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            const double2 d = q[i * Vh + h];
+            u[i] = {(R)d.x, (R)d.y};
+        }
+    } else if constexpr (sizeof(S) == 4) {
+        const float4 *q = (const float4 *)base + mp * 4 * Vh;
+        const float2 *t = (const float2 *)((const float4 *)base + 32 * Vh) + mp * Vh;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float4 f = q[k * Vh + h];
+            u[2 * k] = {(R)f.x, (R)f.y};
+            u[2 * k + 1] = {(R)f.z, (R)f.w};
+        }
+        const float2 f = t[h];
+        u[8] = {(R)f.x, (R)f.y};
+    } else {
+        const uint4 *q = (const uint4 *)base + mp * 2 * Vh;
+        const uint32_t *t = (const uint32_t *)((const uint4 *)base + 16 * Vh) + mp * Vh;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const uint4 w = q[k * Vh + h];
+            float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w);
+            u[4 * k + 0] = {(R)a.x, (R)a.y};
+            u[4 * k + 1] = {(R)b.x, (R)b.y};
+            u[4 * k + 2] = {(R)c.x, (R)c.y};
+            u[4 * k + 3] = {(R)d.x, (R)d.y};
+        }
+        const float2 f = h2f2(t[h]);
+        u[8] = {(R)f.x, (R)f.y};
+    }
+}
+
+template <typename S, typename R>
+WCL_D void store_link(void *base, int mu, int p, size_t h, size_t Vh, const cplx<R> u[9])
+{
+    const size_t mp = (size_t)(mu * 2 + p);
+    if constexpr (sizeof(S) == 8) {
+        double2 *q = (double2 *)base + mp * 9 * Vh;
+#pragma unroll
+        for (int i = 0; i < 9; i++) q[i * Vh + h] = make_double2((double)u[i].re, (double)u[i].im);
+    } else if constexpr (sizeof(S) == 4) {
+        float4 *q = (float4 *)base + mp * 4 * Vh;
+        float2 *t = (float2 *)((float4 *)base + 32 * Vh) + mp * Vh;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            q[k * Vh + h] = make_float4((float)u[2 * k].re, (float)u[2 * k].im, (float)u[2 * k + 1].re,
+                                        (float)u[2 * k + 1].im);
+        t[h] = make_float2((float)u[8].re, (float)u[8].im);
+    } else {
+        uint4 *q = (uint4 *)base + mp * 2 * Vh;
+        uint32_t *t = (uint32_t *)((uint4 *)base + 16 * Vh) + mp * Vh;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            uint4 w;
+            w.x = f22h((float)u[4 * k].re, (float)u[4 * k].im);
+            w.y = f22h((float)u[4 * k + 1].re, (float)u[4 * k + 1].im);
+            w.z = f22h((float)u[4 * k + 2].re, (float)u[4 * k + 2].im);
+            w.w = f22h((float)u[4 * k + 3].re, (float)u[4 * k + 3].im);
+            q[k * Vh + h] = w;
+        }
+        t[h] = f22h((float)u[8].re, (float)u[8].im);
+    }
+}
+
+// Bytes of one link field (both parities, 4 directions) in storage S.
+WCL_HD size_t link_bytes(int S_size, size_t Vh)
+{
+    return S_size == 8 ? 72 * 16 * Vh : S_size == 4 ? (32 * 16 + 8 * 8) * Vh : (16 * 16 + 8 * 4) * Vh;
+}
+WCL_HD size_t spinor_bytes(int S_size, size_t Vh) { return (S_size == 8 ? 192 : S_size == 4 ? 96 : 48) * Vh; }
+WCL_HD size_t clover_bytes(int S_size, size_t Vh) { return 2 * (S_size == 8 ? 576 : S_size == 4 ? 288 : 144) * Vh; }
+
+// Clover site (72 reals) at (parity p, h).
+template <typename S, typename R>
+WCL_D void load_clover(const void *base, int p, size_t h, size_t Vh, R c[72])
+{
+    if constexpr (sizeof(S) == 8) {
+        const double2 *q = (const double2 *)base + (size_t)p * 36 * Vh;
+#pragma unroll
+        for (int k = 0; k < 36; k++) {
+            const double2 d = q[k * Vh + h];
+            c[2 * k] = (R)d.x;
+            c[2 * k + 1] = (R)d.y;
+        }
+    } else if constexpr (sizeof(S) == 4) {
+        const float4 *q = (const float4 *)base + (size_t)p * 18 * Vh;
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            const float4 f = q[k * Vh + h];
+            c[4 * k] = f.x; c[4 * k + 1] = f.y; c[4 * k + 2] = f.z; c[4 * k + 3] = f.w;
+        }
+    } else {
+        const uint4 *q = (const uint4 *)base + (size_t)p * 9 * Vh;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const uint4 w = q[k * Vh + h];
+            float2 a = h2f2(w.x), b = h2f2(w.y), cc = h2f2(w.z), d = h2f2(w.w);
+            c[8 * k + 0] = a.x; c[8 * k + 1] = a.y; c[8 * k + 2] = b.x; c[8 * k + 3] = b.y;
+            c[8 * k + 4] = cc.x; c[8 * k + 5] = cc.y; c[8 * k + 6] = d.x; c[8 * k + 7] = d.y;
+        }
+    }
+}
+
+template <typename S>
+WCL_D void store_clover(void *base, int p, size_t h, size_t Vh, const double c[72])
+{
+    if constexpr (sizeof(S) == 8) {
+        double2 *q = (double2 *)base + (size_t)p * 36 * Vh;
+#pragma unroll
+        for (int k = 0; k < 36; k++) q[k * Vh + h] = make_double2(c[2 * k], c[2 * k + 1]);
+    } else if constexpr (sizeof(S) == 4) {
+        float4 *q = (float4 *)base + (size_t)p * 18 * Vh;
+#pragma unroll
+        for (int k = 0; k < 18; k++)
+            q[k * Vh + h] = make_float4((float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]);
+    } else {
+        uint4 *q = (uint4 *)base + (size_t)p * 9 * Vh;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            uint4 w;
+            w.x = f22h((float)c[8 * k], (float)c[8 * k + 1]);
+            w.y = f22h((float)c[8 * k + 2], (float)c[8 * k + 3]);
+            w.z = f22h((float)c[8 * k + 4], (float)c[8 * k + 5]);
+            w.w = f22h((float)c[8 * k + 6], (float)c[8 * k + 7]);
+            q[k * Vh + h] = w;
+        }
+    }
+}
+
+// out = A v for a packed Hermitian clover site (two 6x6 blocks): 504 flop.
+template <typename R>
+WCL_D void clover_mul(const R c[72], const cplx<R> v[12], cplx<R> out[12])
+{
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        const R *blk = c + 36 * b;
+        const cplx<R> *x = v + 6 * b;
+        cplx<R> *y = out + 6 * b;
+#pragma unroll
+        for (int i = 0; i < 6; i++) y[i] = blk[i] * x[i];
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+#pragma unroll
+            for (int j = i + 1; j < 6; j++) {
+                const cplx<R> a = {blk[6 + 2 * k], blk[7 + 2 * k]};
+                y[i] = cfma(a, x[j], y[i]);
+                y[j] = cjfma(a, x[i], y[j]);
+                k++;
+            }
+    }
+}
+
+// SU(3) (or any 3x3) times the two colour vectors of a half spinor.
+template <typename R>
+WCL_D void su3_mul(const cplx<R> u[9], const cplx<R> h[6], cplx<R> o[6])
+{
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cplx<R> acc = u[a * 3] * h[s * 3];
+            acc = cfma(u[a * 3 + 1], h[s * 3 + 1], acc);
+            acc = cfma(u[a * 3 + 2], h[s * 3 + 2], acc);
+            o[s * 3 + a] = acc;
+        }
+}
+
+template <typename R>
+WCL_D void su3_dag_mul(const cplx<R> u[9], const cplx<R> h[6], cplx<R> o[6])
+{
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cplx<R> acc = conjm(u[a], h[s * 3]);
+            acc = cjfma(u[3 + a], h[s * 3 + 1], acc);
+            acc = cjfma(u[6 + a], h[s * 3 + 2], acc);
+            o[s * 3 + a] = acc;
+        }
+}
+
+// XCD-aware workgroup order: consecutive logical tiles land on one XCD
+// (workgroups are dealt round-robin over the 8 XCDs).
+WCL_D int xcd_block(int bid, int nblk)
+{
+    const int per = nblk >> 3;
+    if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+    return bid;
+}
+
+}  // namespace wcl

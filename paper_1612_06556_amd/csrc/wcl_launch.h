@@ -1,0 +1,132 @@
+// wcl_launch.h -- host-side launchers of the library's kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wcl_common.h"
+
+namespace wcl {
+
+// Storage precision codes.
+enum Prec { P64 = 64, P32 = 32, P16 = 16 };
+
+inline int prec_bytes(int prec) { return prec == P64 ? 8 : prec == P32 ? 4 : 2; }
+
+// Epilogues of the hopping kernel; acc = H_{p,1-p} in (projectors swapped
+// when dagger):
+//   HOP      out = acc
+//   CLOV_H   out = A acc                 (A = packed clover field, parity p)
+//   XPAY     out = x + coef * A acc      (Schur second half)
+//   CLOVX    out = A x + coef * acc      (one parity of the full operator)
+enum HopMode { HOP = 0, CLOV_H = 1, XPAY = 2, CLOVX = 3 };
+
+struct HopLaunch {
+    const Geom *g;
+    int link_prec;      // storage of links and clover
+    int spin_prec;      // storage of in / out / x
+    int mode;
+    int dagger;
+    int p;              // output parity
+    const void *in;     // parity 1-p
+    void *out;          // parity p
+    const void *links;
+    const void *clov;   // parity-major clover field (mode != HOP)
+    const void *x;      // parity p (XPAY, CLOVX)
+    double coef;
+    int nrhs;           // right-hand sides, fields strided by *_stride bytes
+    size_t in_stride, out_stride, x_stride;
+    int xcd;            // XCD-aware workgroup order
+    int block;          // threads per workgroup (64..256)
+    const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
+};
+
+hipError_t launch_hop(const HopLaunch &a, hipStream_t st);
+
+// out = A in on parity p (A = clover field).
+hipError_t launch_clover(const Geom &g, int link_prec, int spin_prec, int p, const void *clov,
+                         const void *in, void *out, hipStream_t st);
+
+// Canonical complex128 [V][4][3] <-> e/o FP64 field [2][12][Vh] double2.
+hipError_t launch_pack_spinor(const Geom &g, const double *canon, void *eo, hipStream_t st);
+hipError_t launch_unpack_spinor(const Geom &g, const void *eo, double *canon, hipStream_t st);
+// Canonical U [V][4][3][3] -> internal link fields (any null pointer skipped).
+hipError_t launch_ingest_gauge(const Geom &g, const double *canon, void *u64, void *u32, void *u16,
+                               hipStream_t st);
+// Clover T and T^-1 (FP64 arithmetic) from the FP64 links, written in all
+// three precisions.  info_dev[0] counts sites whose 6x6 block lost positive
+// definiteness during inversion (a zero or negative pivot).
+hipError_t launch_clover_build(const Geom &g, const void *u64, double csw_kappa, void *t64, void *ti64,
+                               void *t32, void *ti32, void *t16, void *ti16, int *info_dev,
+                               hipStream_t st);
+
+// Spinor precision conversion of n sites (both layouts hold 12 complex per
+// site): out = scale * in, with scale read from scale_dev (if non-null, as
+// 1 / sqrt(*scale_dev) when inv_sqrt) times scale_host.
+hipError_t launch_convert(int in_prec, int out_prec, size_t nsites, size_t Vh_in, size_t Vh_out,
+                          const void *in, void *out, const double *scale_dev, int inv_sqrt,
+                          double scale_host, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Reductions and BLAS-1 on flat complex arrays (length n complex numbers).
+// Partials are written per workgroup in double; finalisers combine them in
+// a fixed order (bitwise reproducible).
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+
+// Solver scalars on the device (per right-hand side, FP64).
+struct Scalars {
+    double rho[2], rho_old[2], alpha[2], omega[2];
+    double r2, b2, stop2;        // |r|^2, |b|^2 of the current right-hand side, stop threshold^2
+    double scale;                // normalisation of the inner right-hand side
+    double t[8];                 // spare scalars for reductions
+    int done;                    // 1 converged, 2 breakdown
+    int iter;
+    int pad[2];
+};
+
+// dot partials: for each (a_k, b_k) pair listed, sum conj(a_k) b_k.
+hipError_t launch_dots(int prec, size_t n, int npairs, const void *const *a, const void *const *b,
+                       double *partials, const Scalars *sc, hipStream_t st);
+
+// BiCGStab building blocks (complex scalars taken from Scalars).
+enum BicgStep {
+    BICG_INIT_RHO = 0,   // rho = <rt, r>, r2 = |r|^2, b2 = r2, rho_old = alpha = omega = 1, iter = 0
+    BICG_ALPHA = 1,      // alpha = rho / <rt, v>
+    BICG_OMEGA = 2,      // omega = <t, s> / <t, t>
+    BICG_RHO = 3,        // rho_old = rho; rho = <rt, r>; r2 = |r|^2; done if r2 <= stop2 b2
+    NORM_ONLY = 4,       // t[0] = |v|^2
+};
+hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st);
+
+// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
+hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
+                         hipStream_t st);
+// s = r - alpha v
+hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void *s, const Scalars *sc,
+                         hipStream_t st);
+// x += alpha ph + omega sh ; r = s - omega t
+hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r,
+                          const void *s, const void *t, const Scalars *sc, hipStream_t st);
+
+// Generic complex axpby: y = a x + b y, a and b host constants.
+hipError_t launch_axpby(int prec, size_t n, double2 a, const void *x, double2 b, void *y, hipStream_t st);
+hipError_t launch_copy(int prec, size_t n, const void *x, void *y, hipStream_t st);
+hipError_t launch_zero(int prec, size_t n, void *y, hipStream_t st);
+
+// Overlapped RAS block solve: out_e = M in_e (FP32 arithmetic).
+struct RasLaunch {
+    const Geom *g;
+    int overlap;
+    int iters;
+    int link_prec;
+    const void *in;      // FP32 even field
+    void *out;           // FP32 even field
+    const void *links;
+    const void *clov_inv;
+    float kappa2;
+    const Scalars *sc;   // may be null; skips when sc->done
+};
+hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
+int ras_threads(const Geom &g, int overlap);
+
+}  // namespace wcl

@@ -1,0 +1,34 @@
+"""The C-ABI library loads and exports every symbol declared in include/wcl.h
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "wcl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wcl_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["wcl_create", "wcl_set_gauge", "wcl_set_params", "wcl_apply", "wcl_apply_op", "wcl_solve",
+              "wcl_grad", "wcl_bench_hop", "wcl_last_error", "wcl_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1612_06556_amd import wcl
+    if not os.path.exists(wcl.LIB_PATH):
+        pytest.fail("libwcl.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(wcl.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    opts = wcl.wcl_default_opts()
+    assert opts.tol == 1e-10 and opts.use_ras == 1 and opts.ras_iters == 4
+    assert ctypes.sizeof(wcl.wcl_solve_info) == 32

@@ -1,0 +1,130 @@
+"""GPU solves against the FP64 oracle (through wcl_solve).
+
+Bar: final x within 1e-8 (relative) of the oracle's solution converged to
+1e-13, at a true FP64 residual <= 1e-10 measured by the oracle's own D.
+Iteration counts are reported, not compared (they depend on rounding)."""
+import numpy as np
+import pytest
+
+from gpu_util import rel, setup, to_gpu, to_host
+from paper_1612_06556_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_residual(orc, x, b):
+    return float(np.linalg.norm(b - orc.D(x)) / np.linalg.norm(b))
+
+
+_ref_cache = {}
+
+
+def _reference(orc, b, key):
+    if key not in _ref_cache:
+        x, info = orc.bicgstab_eo(b, 1e-13, 20000)
+        assert info["status"] == 0
+        _ref_cache[key] = x
+    return _ref_cache[key]
+
+
+def test_plain_fp64_8x4():
+    """Plain FP64 BiCGStab on the full D, 8^4, kappa 0.12, tol 1e-10."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = synth.gaussian_spinor(dims, 2001)
+    x, info, rc = lat.solve(to_gpu(b), outer=wcl.OUTER_PLAIN64, tol=1e-10, max_outer=5000)
+    x = to_host(x)
+    print("plain64", info, flush=True)
+    assert rc == 0 and info["status"] == 0
+    assert _oracle_residual(orc, x, b) <= 1e-10
+    assert rel(x, _reference(orc, b, "8a")) <= 1e-8
+
+
+@pytest.mark.parametrize("outer,use_ras,inner_prec", [(0, 1, 32), (0, 0, 32), (1, 1, 32), (0, 1, 16), (1, 0, 16)])
+def test_mixed_8x4(outer, use_ras, inner_prec):
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = synth.gaussian_spinor(dims, 2001)
+    x, info, rc = lat.solve(to_gpu(b), outer=outer, use_ras=use_ras, inner_prec=inner_prec, tol=1e-10,
+                            inner_tol=1e-2, max_outer=200)
+    x = to_host(x)
+    print(f"mixed outer={outer} ras={use_ras} prec={inner_prec}", info, flush=True)
+    assert rc == 0 and info["status"] == 0
+    assert _oracle_residual(orc, x, b) <= 1e-10
+    assert rel(x, _reference(orc, b, "8a")) <= 1e-8
+
+
+def test_mixed_ras_16x32():
+    """16^3x32, kappa 0.125: FP64 flexible BiCGStab + FP32 RAS-BiCGStab (4^4, overlap 1, 4 MR)."""
+    dims = (16, 16, 16, 32)
+    lat, orc, _ = setup(dims, -1, 0.125, 1.0, 1002, None)
+    b = synth.gaussian_spinor(dims, 2002)
+    gb = to_gpu(b)
+    # FP32 D error against the oracle
+    e = rel(to_host(lat.apply(gb, prec=32)), orc.D(b))
+    print(f"D fp32 16^3x32 rel={e:.3e}", flush=True)
+    assert e <= 1e-6
+    x, info, rc = lat.solve(gb, tol=1e-10, inner_tol=1e-2, use_ras=1)
+    x = to_host(x)
+    print("mixed 16^3x32", info, flush=True)
+    assert rc == 0
+    assert _oracle_residual(orc, x, b) <= 1e-10
+    err = rel(x, _reference(orc, b, "16"))
+    print(f"x error vs oracle {err:.3e}", flush=True)
+    assert err <= 1e-8
+
+
+def test_solve_edge_cases():
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    zero = np.zeros((np.prod(dims), 4, 3), complex)
+    x, info, rc = lat.solve(to_gpu(zero))
+    assert rc == 0 and np.abs(to_host(x)).max() == 0.0
+    nan = synth.gaussian_spinor(dims, 3)
+    nan[5, 1, 2] = np.nan
+    x, info, rc = lat.solve(to_gpu(nan), raise_on_error=False)
+    assert rc == wcl.WCL_ENAN
+    b = synth.gaussian_spinor(dims, 4)
+    x, info, rc = lat.solve(to_gpu(b), max_outer=1, inner_tol=0.5, max_inner=2, raise_on_error=False)
+    assert rc == wcl.WCL_ENOCONV and info["status"] == wcl.WCL_ENOCONV
+    assert np.isfinite(to_host(x)).all()
+    # two right-hand sides in one call
+    bb = synth.gaussian_spinor(dims, 6, nrhs=2)
+    x, infos, rc = lat.solve(to_gpu(bb))
+    assert rc == 0 and len(infos) == 2
+    for k in range(2):
+        assert _oracle_residual(orc, to_host(x)[k], bb[k]) <= 1e-10
+
+
+def test_singular_free_field_terminates():
+    """U = 1, periodic, kappa = 1/8: D(p=0) = 1 - 8 kappa = 0 -- the solver
+    must stop with an error status within its iteration limits."""
+    import torch
+    from paper_1612_06556_amd import wcl
+    dims = (4, 4, 4, 4)
+    lat = wcl.Lattice(dims, 1)
+    lat.set_gauge(torch.from_numpy(synth.unit_field(dims)).cuda())
+    lat.set_params(0.125, 1.0)
+    b = np.zeros((256, 4, 3), complex)
+    b[:, 0, 0] = 1.0  # the zero mode
+    x, info, rc = lat.solve(to_gpu(b), outer=wcl.OUTER_PLAIN64, max_outer=50, raise_on_error=False)
+    assert rc != 0
+    x, info, rc = lat.solve(to_gpu(b), max_outer=5, max_inner=20, raise_on_error=False)
+    assert rc != 0
+
+
+def test_invalid_arguments():
+    from paper_1612_06556_amd import wcl
+    with pytest.raises(wcl.WclError):
+        wcl.Lattice((8, 8, 8, 7))
+    with pytest.raises(wcl.WclError):
+        wcl.Lattice((8, 8, 8, 8), tile=(3, 2, 2, 2))
+    lat = wcl.Lattice((8, 8, 8, 8))
+    b = np.zeros((4096, 4, 3), complex)
+    with pytest.raises(wcl.WclError) as e:
+        lat.apply(to_gpu(b))
+    assert e.value.code == wcl.WCL_ESTATE
+    with pytest.raises(wcl.WclError):
+        lat.set_ras(3, 4)  # 4 + 2*3 > 8
