@@ -141,6 +141,32 @@ int wcl_grad(wcl_ctx *ctx, const double *x_dev, const double *y_dev, double *gU_
  * Cache).  *ms_per_call receives the mean launch time from HIP events. */
 int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
 
+/* Kernel-class profiling on the context's stream: with profiling enabled,
+ * every launch of the classes below is bracketed by HIP events and its
+ * algorithmic HBM bytes and flops are recorded (1320 flop per hop site,
+ * 504 per clover site; bytes = each link, clover site and vector once).
+ * wcl_profile(ctx, 1) clears and starts, (ctx, 0) stops; wcl_profile_read
+ * synchronises the stream and returns the totals of one class. */
+enum { WCL_K_HOP = 0, WCL_K_RAS = 1, WCL_K_CLOVER = 2, WCL_K_COUNT = 3 };
+typedef struct {
+    int launches;
+    int pad;
+    double ms;       /* summed event time of the launches */
+    double bytes;    /* summed algorithmic HBM bytes       */
+    double flops;    /* summed flops (conventions above)   */
+} wcl_kstat;
+int wcl_profile(wcl_ctx *ctx, int enable);
+int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
+
+/* Launch configuration of the hopping kernel: threads per workgroup (64, 128,
+ * 256), pipeline depth (2, 3, 4: hops of a site whose neighbour spinor and
+ * link are in flight while an earlier hop is computed) and XCD-aware
+ * workgroup order (0/1).  wcl_autotune_hop times every combination with
+ * wcl_bench_hop (prec, `copies` field sets) and keeps the fastest; best[3]
+ * (may be NULL) receives {block, depth, xcd}. */
+int wcl_set_tuning(wcl_ctx *ctx, int hop_block, int hop_depth, int hop_xcd);
+int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
+
 const char *wcl_last_error(void);
 int wcl_destroy(wcl_ctx *ctx);
 

@@ -65,6 +65,18 @@ struct wcl_ctx {
     double *partials = nullptr; // [6][RED_BLOCKS]
     Scalars *sc = nullptr;      // [2]: outer, inner
     Scalars *sc_host = nullptr; // pinned mirror
+    // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
+    int hop_block = 256, hop_depth = 2, hop_xcd = 1;
+    // event profiling of kernel classes
+    struct Rec {
+        int kclass;
+        hipEvent_t e0, e1;
+        double bytes, flops;
+    };
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    wcl_kstat stats[WCL_K_COUNT];
 };
 
 namespace {
@@ -117,9 +129,64 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     L.spin_prec = sprec;
     L.links = links_for(c, lprec);
     L.nrhs = 1;
-    L.xcd = 1;
-    L.block = 256;
+    L.xcd = c->hop_xcd;
+    L.block = c->hop_block;
+    L.depth = c->hop_depth;
     return L;
+}
+
+hipEvent_t take_event(wcl_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch wrappers: with profiling on, bracket the launch with events and keep
+// its algorithmic bytes and flops.
+template <typename F>
+int profiled(wcl_ctx *c, int kclass, double bytes, double flops, F &&launch)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (!e0 || !e1) return fail(WCL_EHIP, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(e0, c->st));
+    }
+    HIPCHK(launch());
+    if (c->prof) {
+        HIPCHK(hipEventRecord(e1, c->st));
+        c->recs.push_back({kclass, e0, e1, bytes, flops});
+    }
+    return WCL_OK;
+}
+
+int run_hop(wcl_ctx *c, const HopLaunch &L)
+{
+    double b = 0, f = 0;
+    if (c->prof) hop_work(L, &b, &f);
+    return profiled(c, WCL_K_HOP, b, f, [&] { return launch_hop(L, c->st); });
+}
+
+int run_ras(wcl_ctx *c, const RasLaunch &R)
+{
+    double b = 0, f = 0;
+    if (c->prof) ras_work(R, &b, &f);
+    return profiled(c, WCL_K_RAS, b, f, [&] { return launch_ras(R, c->st); });
+}
+
+int run_clover(wcl_ctx *c, int lp, int sp, int p, const void *clov, const void *in, void *out)
+{
+    const double sb = sp == P64 ? 192.0 : sp == P32 ? 96.0 : 48.0;
+    const double cb = lp == P64 ? 576.0 : lp == P32 ? 288.0 : 144.0;
+    return profiled(c, WCL_K_CLOVER, (2 * sb + cb) * c->Vh, 504.0 * c->Vh,
+                    [&] { return launch_clover(c->g, lp, sp, p, clov, in, out, c->st); });
 }
 
 // One parity of the full operator: out_p = A_pp x_p + coef H in_{1-p}
@@ -136,7 +203,7 @@ int full_D_parity(wcl_ctx *c, int lprec, int sprec, int p, const void *field_in,
     L.clov = clov_for(c, lprec);
     L.coef = -c->kappa;
     L.sc = sc;
-    HIPCHK(launch_hop(L, c->st));
+    CHK(run_hop(c, L));
     return WCL_OK;
 }
 
@@ -157,22 +224,22 @@ int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void 
     L.p = 1;
     L.in = in_e;
     L.out = tmp_o;
-    HIPCHK(launch_hop(L, c->st));
+    CHK(run_hop(c, L));
     L.mode = XPAY;
     L.p = 0;
     L.in = tmp_o;
     L.x = in_e;
     L.out = out_e;
     L.coef = -c->kappa * c->kappa;
-    HIPCHK(launch_hop(L, c->st));
+    CHK(run_hop(c, L));
     return WCL_OK;
 }
 
 // bhat_e = A_ee^-1 (b_e + k H_eo A_oo^-1 b_o)  (field b: both parities, FP64)
 int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_e)
 {
-    HIPCHK(launch_clover(c->g, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o, c->st));
-    HIPCHK(launch_clover(c->g, P64, P64, 0, c->Ti64, par(b, P64, c->Vh, 0), tmp_e, c->st));
+    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o));
+    CHK(run_clover(c, P64, P64, 0, c->Ti64, par(b, P64, c->Vh, 0), tmp_e));
     HopLaunch L = hop_base(c, P64, P64);
     L.mode = XPAY;
     L.p = 0;
@@ -181,14 +248,14 @@ int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_
     L.out = bhat_e;
     L.clov = c->Ti64;
     L.coef = c->kappa;
-    HIPCHK(launch_hop(L, c->st));
+    CHK(run_hop(c, L));
     return WCL_OK;
 }
 
 // x_o = A_oo^-1 (b_o + k H_oe x_e) into the odd half of field x (even half = x_e already)
 int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o)
 {
-    HIPCHK(launch_clover(c->g, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o, c->st));
+    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o));
     HopLaunch L = hop_base(c, P64, P64);
     L.mode = XPAY;
     L.p = 1;
@@ -197,7 +264,7 @@ int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o)
     L.out = par(x, P64, c->Vh, 1);
     L.clov = c->Ti64;
     L.coef = c->kappa;
-    HIPCHK(launch_hop(L, c->st));
+    CHK(run_hop(c, L));
     return WCL_OK;
 }
 
@@ -332,6 +399,11 @@ int wcl_destroy(wcl_ctx *c)
     for (Buf &b : c->ws)
         if (b.p) (void)hipFree(b.p);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
+    for (auto &r : c->recs) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
     return WCL_OK;
 }
@@ -427,14 +499,14 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
                 L.p = p;
                 L.in = par(a, sp, Vh, 1 - p);
                 L.out = par(b, sp, Vh, p);
-                HIPCHK(launch_hop(L, c->st));
+                CHK(run_hop(c, L));
             }
             break;
         case WCL_OP_CLOVER:
         case WCL_OP_CLOVER_INV:
             for (int p = 0; p < 2; p++)
-                HIPCHK(launch_clover(c->g, lp, sp, p, op == WCL_OP_CLOVER ? clov_for(c, lp) : clovinv_for(c, lp),
-                                     par(a, sp, Vh, p), par(b, sp, Vh, p), c->st));
+                CHK(run_clover(c, lp, sp, p, op == WCL_OP_CLOVER ? clov_for(c, lp) : clovinv_for(c, lp),
+                               par(a, sp, Vh, p), par(b, sp, Vh, p)));
             break;
         case WCL_OP_SCHUR:
             CHK(schur(c, lp, sp, par(a, sp, Vh, 0), par(b, sp, Vh, 0), sp == P64 ? t64o : par(b, sp, Vh, 2), nullptr));
@@ -457,7 +529,7 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.clov_inv = clovinv_for(c, lp);
             R.kappa2 = (float)(c->kappa * c->kappa);
             R.sc = nullptr;
-            HIPCHK(launch_ras(R, c->st));
+            CHK(run_ras(c, R));
             HIPCHK(launch_zero(P64, 12 * Vh, par(b64, P64, Vh, 1), c->st));
             break;
         }
@@ -556,7 +628,7 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc)
         R.sc = sc;
         R.in = w.p32;
         R.out = w.ph32;
-        HIPCHK(launch_ras(R, c->st));
+        CHK(run_ras(c, R));
         ph = w.ph32;
     }
     CHK(schur(c, lp, P32, ph, w.v32, w.o32, sc));
@@ -569,7 +641,7 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc)
     if (cfg.ras) {
         R.in = w.s32;
         R.out = w.sh32;
-        HIPCHK(launch_ras(R, c->st));
+        CHK(run_ras(c, R));
         sh = w.sh32;
     }
     CHK(schur(c, lp, P32, sh, w.t32, w.o32, sc));
@@ -952,4 +1024,69 @@ extern "C" int wcl_grad(wcl_ctx *c, const double *x, const double *y, double *gU
     (void)x; (void)y; (void)gU; (void)gk;
     if (!c) return fail(WCL_EINVAL, "null context");
     return fail(WCL_EINVAL, "wcl_grad: not available in this build");
+}
+
+// ===========================================================================
+extern "C" int wcl_profile(wcl_ctx *c, int enable)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (auto &r : c->recs) {
+        c->pool.push_back(r.e0);
+        c->pool.push_back(r.e1);
+    }
+    c->recs.clear();
+    memset(c->stats, 0, sizeof(c->stats));
+    c->prof = enable != 0;
+    return WCL_OK;
+}
+
+extern "C" int wcl_profile_read(wcl_ctx *c, int kclass, wcl_kstat *out)
+{
+    if (!c || !out || kclass < 0 || kclass >= WCL_K_COUNT) return fail(WCL_EINVAL, "bad argument");
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (auto &r : c->recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+        wcl_kstat &k = c->stats[r.kclass];
+        k.launches += 1;
+        k.ms += ms;
+        k.bytes += r.bytes;
+        k.flops += r.flops;
+        c->pool.push_back(r.e0);
+        c->pool.push_back(r.e1);
+    }
+    c->recs.clear();
+    *out = c->stats[kclass];
+    return WCL_OK;
+}
+
+extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_xcd)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    if (hop_block != 64 && hop_block != 128 && hop_block != 256) return fail(WCL_EINVAL, "hop_block must be 64, 128 or 256");
+    if (hop_depth < 2 || hop_depth > 4) return fail(WCL_EINVAL, "hop_depth must be 2, 3 or 4");
+    c->hop_block = hop_block;
+    c->hop_depth = hop_depth;
+    c->hop_xcd = hop_xcd ? 1 : 0;
+    return WCL_OK;
+}
+
+extern "C" int wcl_autotune_hop(wcl_ctx *c, int prec, int copies, int *best)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    const int blocks[3] = {64, 128, 256}, depths[3] = {2, 3, 4};
+    double best_ms = 1e30;
+    int bb = c->hop_block, bo = c->hop_depth, bx = c->hop_xcd;
+    for (int xcd = 0; xcd < 2; xcd++)
+        for (int ib = 0; ib < 3; ib++)
+            for (int io = 0; io < 3; io++) {
+                CHK(wcl_set_tuning(c, blocks[ib], depths[io], xcd));
+                double ms;
+                CHK(wcl_bench_hop(c, prec, 50, copies, &ms));
+                if (ms < best_ms) { best_ms = ms; bb = blocks[ib]; bo = depths[io]; bx = xcd; }
+            }
+    CHK(wcl_set_tuning(c, bb, bo, bx));
+    if (best) { best[0] = bb; best[1] = bo; best[2] = bx; }
+    return WCL_OK;
 }

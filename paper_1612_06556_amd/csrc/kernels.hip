@@ -362,42 +362,90 @@ struct HopArgs {
     const Scalars *sc;
 };
 
-template <typename SL, typename SS, int MU, int SG, typename R>
-WCL_D void hop_dir(const HopArgs &a, const Site &s, size_t h, cplx<R> acc[12], const char *in)
+// The 8 hops of a site run as a two-stage pipeline: the neighbour spinor and
+// link of hop k+1 are in flight while hop k is computed; a scheduling barrier
+// after each hop keeps the compiler from hoisting further loads (which would
+// raise the register count and lower the occupancy).
+template <typename R>
+struct HopStage {
+    cplx<R> psi[12];
+    cplx<R> u[9];
+    R sign;
+};
+
+// hop K: direction MU = K/2, forward (K even) or backward (K odd)
+// The load offsets of hop K pass through an empty asm that also "rewrites"
+// the accumulator: the loads of hop K then wait for the complete compute of
+// hop K-2, so at most two hops' operands are live at a time (no instruction
+// is emitted for the fence itself).
+template <typename R>
+WCL_D void pipeline_fence(cplx<R> acc[12], uint32_t &hn, uint32_t &h)
 {
+    asm volatile(""
+                 : "+v"(acc[0].re), "+v"(acc[0].im), "+v"(acc[1].re), "+v"(acc[1].im), "+v"(acc[2].re),
+                   "+v"(acc[2].im), "+v"(acc[3].re), "+v"(acc[3].im), "+v"(acc[4].re), "+v"(acc[4].im),
+                   "+v"(acc[5].re), "+v"(acc[5].im), "+v"(acc[6].re), "+v"(acc[6].im), "+v"(acc[7].re),
+                   "+v"(acc[7].im), "+v"(acc[8].re), "+v"(acc[8].im), "+v"(acc[9].re), "+v"(acc[9].im),
+                   "+v"(acc[10].re), "+v"(acc[10].im), "+v"(acc[11].re), "+v"(acc[11].im), "+v"(hn), "+v"(h));
+}
+
+template <typename SL, typename SS, int K, typename R>
+WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, HopStage<R> &st,
+                    cplx<R> acc[12])
+{
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
     const Geom &g = a.g;
-    const size_t Vh = g.Vh;
-    // forward: (1 - SG g_mu) U_mu(x) psi(x + mu)
-    {
-        const int hf = neighbour(g, s, MU, +1);
-        cplx<R> psi[12], hh[6], uh[6], u[9];
-        load_spinor<SS, R>(in, hf, Vh, psi);
-        load_link<SL, R>(a.links, MU, a.p, h, Vh, u);
-        project<MU, -SG, R>(psi, hh);
-        if (MU == 3 && g.tbc < 0 && s.x[3] == g.L[3] - 1) {
+    const uint32_t Vh = g.Vh;
+    uint32_t hn = (uint32_t)neighbour(g, s, MU, FWD ? +1 : -1);
+    uint32_t h = h0;
+    pipeline_fence(acc, hn, h);
+    load_spinor<SS, R>(in, hn, Vh, st.psi);
+    if (FWD) load_link<SL, R>(a.links, MU, a.p, h, Vh, st.u);
+    else load_link<SL, R>(a.links, MU, 1 - a.p, hn, Vh, st.u);
+    st.sign = R(1);
+    if (MU == 3 && g.tbc < 0 && s.x[3] == (FWD ? g.L[3] - 1 : 0)) st.sign = R(-1);
+}
+
+// forward: (1 - SG g_mu) U_mu(x) psi(x+mu);  backward: (1 + SG g_mu) U_mu(x-mu)^dag psi(x-mu)
+template <int K, int SG, typename R>
+WCL_D void hop_compute(const HopStage<R> &st, cplx<R> acc[12])
+{
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
+    constexpr int S = FWD ? -SG : SG;
+    cplx<R> hh[6], uh[6];
+    project<MU, S, R>(st.psi, hh);
 #pragma unroll
-            for (int k = 0; k < 6; k++) hh[k] = -hh[k];
-        }
-        su3_mul(u, hh, uh);
-        accumulate<MU, -SG, R>(acc, uh);
-    }
-    // backward: (1 + SG g_mu) U_mu(x - mu)^dag psi(x - mu)
-    {
-        const int hb = neighbour(g, s, MU, -1);
-        cplx<R> psi[12], hh[6], uh[6], u[9];
-        load_spinor<SS, R>(in, hb, Vh, psi);
-        load_link<SL, R>(a.links, MU, 1 - a.p, hb, Vh, u);
-        project<MU, SG, R>(psi, hh);
-        if (MU == 3 && g.tbc < 0 && s.x[3] == 0) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) hh[k] = -hh[k];
-        }
-        su3_dag_mul(u, hh, uh);
-        accumulate<MU, SG, R>(acc, uh);
+    for (int k = 0; k < 6; k++) hh[k] = st.sign * hh[k];
+    if (FWD) su3_mul(st.u, hh, uh);
+    else su3_dag_mul(st.u, hh, uh);
+    accumulate<MU, S, R>(acc, uh);
+}
+
+template <typename SL, typename SS, int SG, int D, int K, typename R>
+WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
+                        cplx<R> acc[12])
+{
+    if constexpr (K < D - 1) {
+        hop_load<SL, SS, K, R>(a, s, h, in, st[K], acc);
+        hop_prologue<SL, SS, SG, D, K + 1, R>(a, s, h, in, st, acc);
     }
 }
 
-template <typename SL, typename SS, int MODE, bool DAG>
+// hop K is computed while the operands of hop K + D - 1 are in flight
+template <typename SL, typename SS, int SG, int D, int K, typename R>
+WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
+                        cplx<R> acc[12])
+{
+    if constexpr (K < 8) {
+        if constexpr (K + D - 1 < 8) hop_load<SL, SS, K + D - 1, R>(a, s, h, in, st[(K + D - 1) % D], acc);
+        hop_compute<K, SG, R>(st[K % D], acc);
+        hop_pipeline<SL, SS, SG, D, K + 1, R>(a, s, h, in, st, acc);
+    }
+}
+
+template <typename SL, typename SS, int MODE, bool DAG, int DEPTH>
 __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 {
     using R = typename Real<SL>::T;
@@ -413,10 +461,9 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     cplx<R> acc[12];
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = {R(0), R(0)};
-    hop_dir<SL, SS, 0, SG, R>(a, s, h, acc, in);
-    hop_dir<SL, SS, 1, SG, R>(a, s, h, acc, in);
-    hop_dir<SL, SS, 2, SG, R>(a, s, h, acc, in);
-    hop_dir<SL, SS, 3, SG, R>(a, s, h, acc, in);
+    HopStage<R> st[DEPTH];
+    hop_prologue<SL, SS, SG, DEPTH, 0, R>(a, s, h, in, st, acc);
+    hop_pipeline<SL, SS, SG, DEPTH, 0, R>(a, s, h, in, st, acc);
 
     if constexpr (MODE == HOP) {
         store_spinor<SS, R>(out, h, Vh, acc);
@@ -445,11 +492,15 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     }
 }
 
+// Pipeline-depth variants (hops whose operands are in flight: 2, 3, 4).
+// D^dag launches use depth 2 only.
 template <typename SL, typename SS, int MODE>
 static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
 {
-    if (L.dagger) k_hop<SL, SS, MODE, true><<<grid, block, 0, st>>>(a);
-    else k_hop<SL, SS, MODE, false><<<grid, block, 0, st>>>(a);
+    if (L.dagger) k_hop<SL, SS, MODE, true, 2><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 4) k_hop<SL, SS, MODE, false, 4><<<grid, block, 0, st>>>(a);
+    else k_hop<SL, SS, MODE, false, 2><<<grid, block, 0, st>>>(a);
 }
 
 template <typename SL, typename SS>
@@ -853,6 +904,32 @@ hipError_t launch_zero(int prec, size_t n, void *y, hipStream_t st)
     if (prec == P64) k_zero<double><<<blas_grid(n), 256, 0, st>>>(n, (double2 *)y);
     else k_zero<float><<<blas_grid(n), 256, 0, st>>>(n, (float2 *)y);
     return hipGetLastError();
+}
+
+}  // namespace wcl
+
+namespace wcl {
+
+static double link_site_bytes(int prec) { return prec == P64 ? 144.0 : prec == P32 ? 72.0 : 36.0; }
+static double spinor_site_bytes(int prec) { return prec == P64 ? 192.0 : prec == P32 ? 96.0 : 48.0; }
+static double clover_site_bytes(int prec) { return prec == P64 ? 576.0 : prec == P32 ? 288.0 : 144.0; }
+
+void hop_work(const HopLaunch &a, double *bytes, double *flops)
+{
+    const double sites = (double)a.g->Vh * (a.nrhs > 0 ? a.nrhs : 1);
+    double b = (a.nrhs > 0 ? 8.0 * link_site_bytes(a.link_prec) / a.nrhs : 8.0 * link_site_bytes(a.link_prec));
+    b += 2.0 * spinor_site_bytes(a.spin_prec);
+    double f = 1320.0;
+    if (a.mode != HOP) {
+        b += clover_site_bytes(a.link_prec) / (a.nrhs > 0 ? a.nrhs : 1);
+        f += 504.0;
+    }
+    if (a.mode == XPAY || a.mode == CLOVX) {
+        b += spinor_site_bytes(a.spin_prec);
+        f += 48.0;
+    }
+    *bytes = b * sites;
+    *flops = f * sites;
 }
 
 }  // namespace wcl

@@ -313,3 +313,28 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
 }
 
 }  // namespace wcl
+
+namespace wcl {
+
+void ras_work(const RasLaunch &L, double *bytes, double *flops)
+{
+    const Geom &g = *L.g;
+    const double lb = L.link_prec == P32 ? 72.0 : 36.0, cb = L.link_prec == P32 ? 288.0 : 144.0;
+    *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + 2.0 * 96.0);
+    int e[4];
+    double ext = 1.0;
+    for (int mu = 0; mu < 4; mu++) {
+        e[mu] = g.B[mu] + 2 * L.overlap;
+        ext *= e[mu];
+    }
+    double hops = 0.0;  // directed in-block hops per block and iteration, both parities
+    for (int mu = 0; mu < 4; mu++) hops += 2.0 * (e[mu] - 1) * ext / e[mu];
+    const double ne = ext / 2.0;
+    // per iteration: hops, clover on every site, q = r - k^2 w (48 per even site),
+    // two dot products (96) and the z, r updates (96)
+    const double per_iter = hops * 168.0 + ext * 504.0 + ne * (48.0 + 96.0 + 96.0);
+    const double nblk = (double)g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
+    *flops = per_iter * L.iters * nblk;
+}
+
+}  // namespace wcl

@@ -233,29 +233,39 @@ WCL_D uint32_t f22h(float a, float b)
     return *reinterpret_cast<uint32_t *>(&h);
 }
 
+// Every field access is a uniform base pointer plus a 32-bit byte offset
+// (fields are below 4 GiB), which keeps one VGPR per address instead of two.
+template <typename T>
+WCL_D T ldf(const void *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T>
+WCL_D void stf(void *base, uint32_t off, const T &v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
 template <typename S, typename R>
-WCL_D void load_spinor(const void *base, size_t h, size_t Vh, cplx<R> v[12])
+WCL_D void load_spinor(const void *base, uint32_t h, uint32_t Vh, cplx<R> v[12])
 {
     if constexpr (sizeof(S) == 8) {
-        const double2 *p = (const double2 *)base;
 #pragma unroll
-        for (int i = 0; i < 12; i++) {
-            const double2 d = p[i * Vh + h];
+        for (uint32_t i = 0; i < 12; i++) {
+            const double2 d = ldf<double2>(base, (i * Vh + h) * 16u);
             v[i] = {(R)d.x, (R)d.y};
         }
     } else if constexpr (sizeof(S) == 4) {
-        const float4 *p = (const float4 *)base;
 #pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const float4 f = p[k * Vh + h];
+        for (uint32_t k = 0; k < 6; k++) {
+            const float4 f = ldf<float4>(base, (k * Vh + h) * 16u);
             v[2 * k] = {(R)f.x, (R)f.y};
             v[2 * k + 1] = {(R)f.z, (R)f.w};
         }
     } else {
-        const uint4 *p = (const uint4 *)base;
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const uint4 u = p[k * Vh + h];
+        for (uint32_t k = 0; k < 3; k++) {
+            const uint4 u = ldf<uint4>(base, (k * Vh + h) * 16u);
             float2 a = h2f2(u.x), b = h2f2(u.y), c = h2f2(u.z), d = h2f2(u.w);
             v[4 * k + 0] = {(R)a.x, (R)a.y};
             v[4 * k + 1] = {(R)b.x, (R)b.y};
@@ -266,101 +276,89 @@ WCL_D void load_spinor(const void *base, size_t h, size_t Vh, cplx<R> v[12])
 }
 
 template <typename S, typename R>
-WCL_D void store_spinor(void *base, size_t h, size_t Vh, const cplx<R> v[12])
+WCL_D void store_spinor(void *base, uint32_t h, uint32_t Vh, const cplx<R> v[12])
 {
     if constexpr (sizeof(S) == 8) {
-        double2 *p = (double2 *)base;
 #pragma unroll
-        for (int i = 0; i < 12; i++) p[i * Vh + h] = make_double2((double)v[i].re, (double)v[i].im);
+        for (uint32_t i = 0; i < 12; i++) stf(base, (i * Vh + h) * 16u, make_double2((double)v[i].re, (double)v[i].im));
     } else if constexpr (sizeof(S) == 4) {
-        float4 *p = (float4 *)base;
 #pragma unroll
-        for (int k = 0; k < 6; k++)
-            p[k * Vh + h] = make_float4((float)v[2 * k].re, (float)v[2 * k].im, (float)v[2 * k + 1].re,
-                                        (float)v[2 * k + 1].im);
+        for (uint32_t k = 0; k < 6; k++)
+            stf(base, (k * Vh + h) * 16u,
+                make_float4((float)v[2 * k].re, (float)v[2 * k].im, (float)v[2 * k + 1].re, (float)v[2 * k + 1].im));
     } else {
-        uint4 *p = (uint4 *)base;
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
+        for (uint32_t k = 0; k < 3; k++) {
             uint4 u;
             u.x = f22h((float)v[4 * k].re, (float)v[4 * k].im);
             u.y = f22h((float)v[4 * k + 1].re, (float)v[4 * k + 1].im);
             u.z = f22h((float)v[4 * k + 2].re, (float)v[4 * k + 2].im);
             u.w = f22h((float)v[4 * k + 3].re, (float)v[4 * k + 3].im);
-            p[k * Vh + h] = u;
+            stf(base, (k * Vh + h) * 16u, u);
         }
     }
 }
 
 // Link U_mu at (parity p, half index h): 9 complex, row-major.
 template <typename S, typename R>
-WCL_D void load_link(const void *base, int mu, int p, size_t h, size_t Vh, cplx<R> u[9])
+WCL_D void load_link(const void *base, int mu, int p, uint32_t h, uint32_t Vh, cplx<R> u[9])
 {
-    const size_t mp = (size_t)(mu * 2 + p);
+    const uint32_t mp = (uint32_t)(mu * 2 + p);
     if constexpr (sizeof(S) == 8) {
-        const double2 *q = (const double2 *)base + mp * 9 * Vh;
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
-            const double2 d = q[i * Vh + h];
+        for (uint32_t i = 0; i < 9; i++) {
+            const double2 d = ldf<double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
             u[i] = {(R)d.x, (R)d.y};
         }
     } else if constexpr (sizeof(S) == 4) {
-        const float4 *q = (const float4 *)base + mp * 4 * Vh;
-        const float2 *t = (const float2 *)((const float4 *)base + 32 * Vh) + mp * Vh;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const float4 f = q[k * Vh + h];
+        for (uint32_t k = 0; k < 4; k++) {
+            const float4 f = ldf<float4>(base, ((mp * 4 + k) * Vh + h) * 16u);
             u[2 * k] = {(R)f.x, (R)f.y};
             u[2 * k + 1] = {(R)f.z, (R)f.w};
         }
-        const float2 f = t[h];
+        const float2 f = ldf<float2>(base, 32u * Vh * 16u + (mp * Vh + h) * 8u);
         u[8] = {(R)f.x, (R)f.y};
     } else {
-        const uint4 *q = (const uint4 *)base + mp * 2 * Vh;
-        const uint32_t *t = (const uint32_t *)((const uint4 *)base + 16 * Vh) + mp * Vh;
 #pragma unroll
-        for (int k = 0; k < 2; k++) {
-            const uint4 w = q[k * Vh + h];
+        for (uint32_t k = 0; k < 2; k++) {
+            const uint4 w = ldf<uint4>(base, ((mp * 2 + k) * Vh + h) * 16u);
             float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w);
             u[4 * k + 0] = {(R)a.x, (R)a.y};
             u[4 * k + 1] = {(R)b.x, (R)b.y};
             u[4 * k + 2] = {(R)c.x, (R)c.y};
             u[4 * k + 3] = {(R)d.x, (R)d.y};
         }
-        const float2 f = h2f2(t[h]);
+        const float2 f = h2f2(ldf<uint32_t>(base, 16u * Vh * 16u + (mp * Vh + h) * 4u));
         u[8] = {(R)f.x, (R)f.y};
     }
 }
 
 template <typename S, typename R>
-WCL_D void store_link(void *base, int mu, int p, size_t h, size_t Vh, const cplx<R> u[9])
+WCL_D void store_link(void *base, int mu, int p, uint32_t h, uint32_t Vh, const cplx<R> u[9])
 {
-    const size_t mp = (size_t)(mu * 2 + p);
+    const uint32_t mp = (uint32_t)(mu * 2 + p);
     if constexpr (sizeof(S) == 8) {
-        double2 *q = (double2 *)base + mp * 9 * Vh;
 #pragma unroll
-        for (int i = 0; i < 9; i++) q[i * Vh + h] = make_double2((double)u[i].re, (double)u[i].im);
+        for (uint32_t i = 0; i < 9; i++)
+            stf(base, ((mp * 9 + i) * Vh + h) * 16u, make_double2((double)u[i].re, (double)u[i].im));
     } else if constexpr (sizeof(S) == 4) {
-        float4 *q = (float4 *)base + mp * 4 * Vh;
-        float2 *t = (float2 *)((float4 *)base + 32 * Vh) + mp * Vh;
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            q[k * Vh + h] = make_float4((float)u[2 * k].re, (float)u[2 * k].im, (float)u[2 * k + 1].re,
-                                        (float)u[2 * k + 1].im);
-        t[h] = make_float2((float)u[8].re, (float)u[8].im);
+        for (uint32_t k = 0; k < 4; k++)
+            stf(base, ((mp * 4 + k) * Vh + h) * 16u,
+                make_float4((float)u[2 * k].re, (float)u[2 * k].im, (float)u[2 * k + 1].re, (float)u[2 * k + 1].im));
+        stf(base, 32u * Vh * 16u + (mp * Vh + h) * 8u, make_float2((float)u[8].re, (float)u[8].im));
     } else {
-        uint4 *q = (uint4 *)base + mp * 2 * Vh;
-        uint32_t *t = (uint32_t *)((uint4 *)base + 16 * Vh) + mp * Vh;
 #pragma unroll
-        for (int k = 0; k < 2; k++) {
+        for (uint32_t k = 0; k < 2; k++) {
             uint4 w;
             w.x = f22h((float)u[4 * k].re, (float)u[4 * k].im);
             w.y = f22h((float)u[4 * k + 1].re, (float)u[4 * k + 1].im);
             w.z = f22h((float)u[4 * k + 2].re, (float)u[4 * k + 2].im);
             w.w = f22h((float)u[4 * k + 3].re, (float)u[4 * k + 3].im);
-            q[k * Vh + h] = w;
+            stf(base, ((mp * 2 + k) * Vh + h) * 16u, w);
         }
-        t[h] = f22h((float)u[8].re, (float)u[8].im);
+        stf(base, 16u * Vh * 16u + (mp * Vh + h) * 4u, f22h((float)u[8].re, (float)u[8].im));
     }
 }
 
@@ -374,28 +372,25 @@ WCL_HD size_t clover_bytes(int S_size, size_t Vh) { return 2 * (S_size == 8 ? 57
 
 // Clover site (72 reals) at (parity p, h).
 template <typename S, typename R>
-WCL_D void load_clover(const void *base, int p, size_t h, size_t Vh, R c[72])
+WCL_D void load_clover(const void *base, int p, uint32_t h, uint32_t Vh, R c[72])
 {
     if constexpr (sizeof(S) == 8) {
-        const double2 *q = (const double2 *)base + (size_t)p * 36 * Vh;
 #pragma unroll
-        for (int k = 0; k < 36; k++) {
-            const double2 d = q[k * Vh + h];
+        for (uint32_t k = 0; k < 36; k++) {
+            const double2 d = ldf<double2>(base, (((uint32_t)p * 36 + k) * Vh + h) * 16u);
             c[2 * k] = (R)d.x;
             c[2 * k + 1] = (R)d.y;
         }
     } else if constexpr (sizeof(S) == 4) {
-        const float4 *q = (const float4 *)base + (size_t)p * 18 * Vh;
 #pragma unroll
-        for (int k = 0; k < 18; k++) {
-            const float4 f = q[k * Vh + h];
+        for (uint32_t k = 0; k < 18; k++) {
+            const float4 f = ldf<float4>(base, (((uint32_t)p * 18 + k) * Vh + h) * 16u);
             c[4 * k] = f.x; c[4 * k + 1] = f.y; c[4 * k + 2] = f.z; c[4 * k + 3] = f.w;
         }
     } else {
-        const uint4 *q = (const uint4 *)base + (size_t)p * 9 * Vh;
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            const uint4 w = q[k * Vh + h];
+        for (uint32_t k = 0; k < 9; k++) {
+            const uint4 w = ldf<uint4>(base, (((uint32_t)p * 9 + k) * Vh + h) * 16u);
             float2 a = h2f2(w.x), b = h2f2(w.y), cc = h2f2(w.z), d = h2f2(w.w);
             c[8 * k + 0] = a.x; c[8 * k + 1] = a.y; c[8 * k + 2] = b.x; c[8 * k + 3] = b.y;
             c[8 * k + 4] = cc.x; c[8 * k + 5] = cc.y; c[8 * k + 6] = d.x; c[8 * k + 7] = d.y;
@@ -404,27 +399,26 @@ WCL_D void load_clover(const void *base, int p, size_t h, size_t Vh, R c[72])
 }
 
 template <typename S>
-WCL_D void store_clover(void *base, int p, size_t h, size_t Vh, const double c[72])
+WCL_D void store_clover(void *base, int p, uint32_t h, uint32_t Vh, const double c[72])
 {
     if constexpr (sizeof(S) == 8) {
-        double2 *q = (double2 *)base + (size_t)p * 36 * Vh;
 #pragma unroll
-        for (int k = 0; k < 36; k++) q[k * Vh + h] = make_double2(c[2 * k], c[2 * k + 1]);
+        for (uint32_t k = 0; k < 36; k++)
+            stf(base, (((uint32_t)p * 36 + k) * Vh + h) * 16u, make_double2(c[2 * k], c[2 * k + 1]));
     } else if constexpr (sizeof(S) == 4) {
-        float4 *q = (float4 *)base + (size_t)p * 18 * Vh;
 #pragma unroll
-        for (int k = 0; k < 18; k++)
-            q[k * Vh + h] = make_float4((float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]);
+        for (uint32_t k = 0; k < 18; k++)
+            stf(base, (((uint32_t)p * 18 + k) * Vh + h) * 16u,
+                make_float4((float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]));
     } else {
-        uint4 *q = (uint4 *)base + (size_t)p * 9 * Vh;
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
+        for (uint32_t k = 0; k < 9; k++) {
             uint4 w;
             w.x = f22h((float)c[8 * k], (float)c[8 * k + 1]);
             w.y = f22h((float)c[8 * k + 2], (float)c[8 * k + 3]);
             w.z = f22h((float)c[8 * k + 4], (float)c[8 * k + 5]);
             w.w = f22h((float)c[8 * k + 6], (float)c[8 * k + 7]);
-            q[k * Vh + h] = w;
+            stf(base, (((uint32_t)p * 9 + k) * Vh + h) * 16u, w);
         }
     }
 }

@@ -37,10 +37,20 @@ struct HopLaunch {
     size_t in_stride, out_stride, x_stride;
     int xcd;            // XCD-aware workgroup order
     int block;          // threads per workgroup (64..256)
+    int depth;          // hops whose operands are in flight per thread (2, 3, 4)
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
 };
 
 hipError_t launch_hop(const HopLaunch &a, hipStream_t st);
+
+// Algorithmic HBM bytes and flops of one hop launch (per the operator's
+// definition: every link, the input spinor, the clover site and the output
+// once; 1320 flop per hop site, 504 per clover site, 48 per fused axpy).
+void hop_work(const HopLaunch &a, double *bytes, double *flops);
+// Same for one RAS application (bytes: links and clover inverse of both
+// parities, input and output once per even site; flops: the block hops,
+// clover multiplications and minimal-residual vector work actually done).
+void ras_work(const struct RasLaunch &a, double *bytes, double *flops);
 
 // out = A in on parity p (A = clover field).
 hipError_t launch_clover(const Geom &g, int link_prec, int spin_prec, int p, const void *clov,

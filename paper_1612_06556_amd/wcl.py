@@ -46,6 +46,13 @@ class wcl_solve_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class wcl_kstat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int), ("pad", ctypes.c_int), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+K_HOP, K_RAS, K_CLOVER = 0, 1, 2
+
 _lib = None
 _ip = ctypes.POINTER(ctypes.c_int)
 _vp = ctypes.c_void_p
@@ -74,6 +81,10 @@ def load():
     lib.wcl_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
     lib.wcl_bench_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.wcl_destroy.argtypes = [_vp]
+    lib.wcl_profile.argtypes = [_vp, ctypes.c_int]
+    lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
+    lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     _lib = lib
     return lib
 
@@ -149,6 +160,26 @@ def wcl_bench_hop(h, prec, reps, copies):
 
 def wcl_destroy(h):
     load().wcl_destroy(h)
+
+
+def wcl_profile(h, enable):
+    _check(load().wcl_profile(h, int(bool(enable))))
+
+
+def wcl_profile_read(h, kclass):
+    k = wcl_kstat()
+    _check(load().wcl_profile_read(h, int(kclass), ctypes.byref(k)))
+    return {"launches": k.launches, "ms": k.ms, "bytes": k.bytes, "flops": k.flops}
+
+
+def wcl_set_tuning(h, hop_block, hop_depth, hop_xcd):
+    _check(load().wcl_set_tuning(h, int(hop_block), int(hop_depth), int(hop_xcd)))
+
+
+def wcl_autotune_hop(h, prec, copies):
+    best = (ctypes.c_int * 3)()
+    _check(load().wcl_autotune_hop(h, int(prec), int(copies), best))
+    return {"hop_block": best[0], "hop_depth": best[1], "hop_xcd": best[2]}
 
 
 # --- convenience wrapper -----------------------------------------------------
