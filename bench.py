@@ -57,7 +57,7 @@ def cpu_baseline(U, psi, budget_s=15.0):
         orc.D(psi)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
+        if el >= budget_s or n >= 400:
             break
     flops = n * V * (1320.0 + 504.0 + 48.0)
     return {"value": round(flops / el / 1e9, 3), "unit": "GFlop/s", "cores": threads, "kind": "oracle",

@@ -109,6 +109,7 @@ typedef struct {
     int inner_prec;      /* 32: FP32 links/clover; 16: FP16 links/clover (FP32 math) */
     int use_graph;       /* replay the inner iteration as a captured hipGraph        */
     int check_every;     /* inner iterations between host convergence checks         */
+    int adjoint;         /* 1: solve D^dag x = b instead, as x = g5 D^-1 (g5 b)      */
 } wcl_solve_opts;
 
 typedef struct {

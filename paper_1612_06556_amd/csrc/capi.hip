@@ -308,6 +308,8 @@ enum Slot {
     S_RHS32, S_X32, S_R32, S_RT32, S_P32, S_V32, S_S32, S_T32, S_PH32, S_SH32, S_O32,
     // plain FP64 full-field vectors
     S_PR, S_PRT, S_PP, S_PV, S_PS, S_PT, S_PX,
+    // gradient
+    S_GX, S_GY, S_GK, S_GG, S_GHX, S_GCX,
     // bench copies start here
     S_BENCH = 64,
 };
@@ -676,16 +678,42 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
         HIPCHK(launch_dots(P32, n, 2, a, b, c->partials, nullptr, c->st));
         HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st));
     }
-    int done_iters = 0;
-    while (done_iters < cfg.maxit) {
-        const int chunk = std::min(cfg.check_every, cfg.maxit - done_iters);
-        for (int k = 0; k < chunk; k++) CHK(inner_iteration(c, cfg, w, sc));
-        done_iters += chunk;
+    // Iterations are queued in chunks; every kernel of an iteration queued
+    // after convergence is a no-op.  The chunk length follows the observed
+    // convergence rate so that few such iterations are queued.
+    int launched = 0;
+    int chunk = std::min(cfg.check_every, 4);
+    double r2_prev = 1.0;  // |r0|^2 of the normalised right-hand side
+    int it_prev = 0;
+    std::vector<size_t> rec_mark;  // profile records at the start of each queued iteration
+    while (launched < cfg.maxit) {
+        chunk = std::max(1, std::min(chunk, cfg.maxit - launched));
+        for (int k = 0; k < chunk; k++) {
+            rec_mark.push_back(c->recs.size());
+            CHK(inner_iteration(c, cfg, w, sc));
+        }
+        launched += chunk;
         CHK(read_scalars(c, 1));
-        if (c->sc_host[1].done) break;
+        const Scalars &h = c->sc_host[1];
+        if (h.done) break;
+        // predicted iterations to reach the target at the rate seen so far
+        const int di = h.iter - it_prev;
+        if (di > 0 && h.r2 > 0.0 && h.r2 < r2_prev) {
+            const double rate = std::log(h.r2 / r2_prev) / di;
+            const double need = std::log(h.stop2 * h.b2 / h.r2) / rate;
+            chunk = (int)std::min(16.0, std::max(1.0, std::floor(need)));
+        } else {
+            chunk = std::min(cfg.check_every, 4);
+        }
+        r2_prev = h.r2;
+        it_prev = h.iter;
     }
-    if (!c->sc_host[1].done) CHK(read_scalars(c, 1));
     *iters = c->sc_host[1].iter;
+    // launches of iterations past the converged one did no work
+    for (size_t k = (size_t)*iters; k < rec_mark.size(); k++) {
+        const size_t end = (k + 1 < rec_mark.size()) ? rec_mark[k + 1] : c->recs.size();
+        for (size_t r = rec_mark[k]; r < end; r++) c->recs[r].bytes = c->recs[r].flops = 0.0;
+    }
     HIPCHK(launch_convert(P32, P64, Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st));
     return WCL_OK;
 }
@@ -856,9 +884,14 @@ int plain64(wcl_ctx *c, const wcl_solve_opts &o, SolveWs &w, double bnorm2, wcl_
         CHK(set_outer_stop(c, o.tol * o.tol * bnorm2 / r02));
         const int it0 = info.outer_iters;
         bool stop = false;
+        std::vector<size_t> rec_mark;  // profile records at the start of each queued iteration
+        int queued = 0;
         while (info.outer_iters < o.max_outer) {
-            const int chunk = std::min(every, o.max_outer - info.outer_iters);
+            const int chunk = std::min(every, o.max_outer - it0 - queued);
+            if (chunk <= 0) break;
+            queued += chunk;
             for (int k = 0; k < chunk; k++) {
+                rec_mark.push_back(c->recs.size());
                 HIPCHK(launch_bicg_p(P64, n, r, p, v, sc, c->st));
                 CHK(full_D(c, P64, P64, p, v, 0, sc));
                 {
@@ -883,6 +916,10 @@ int plain64(wcl_ctx *c, const wcl_solve_opts &o, SolveWs &w, double bnorm2, wcl_
             CHK(read_scalars(c, 0));
             const Scalars &h = c->sc_host[0];
             info.outer_iters = it0 + h.iter;
+            for (size_t k = (size_t)h.iter; k < rec_mark.size(); k++) {  // no-op launches
+                const size_t end = (k + 1 < rec_mark.size()) ? rec_mark[k + 1] : c->recs.size();
+                for (size_t q = rec_mark[k]; q < end; q++) c->recs[q].bytes = c->recs[q].flops = 0.0;
+            }
             if (!std::isfinite(h.r2)) { info.status = WCL_ENAN; stop = true; break; }
             if (h.done) {
                 double rel;
@@ -933,6 +970,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         const double *bk = b + (size_t)k * c->V * 24;
         double *xk = x + (size_t)k * c->V * 24;
         HIPCHK(launch_pack_spinor(c->g, bk, w.b, c->st));
+        if (o.adjoint) HIPCHK(launch_gamma5(2, c->Vh, w.b, c->st));  // D^dag = g5 D g5
         double bnorm2;
         CHK(norm2_host(c, P64, 24 * (size_t)c->Vh, w.b, &bnorm2));
         if (!std::isfinite(bnorm2)) {
@@ -956,6 +994,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
             if (info.status == WCL_OK && rel > o.tol) info.status = WCL_ENOCONV;
             if (!std::isfinite(rel)) info.status = WCL_ENAN;
         }
+        if (o.adjoint) HIPCHK(launch_gamma5(2, c->Vh, w.x, c->st));
         HIPCHK(launch_unpack_spinor(c->g, w.x, xk, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
         info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1021,9 +1060,43 @@ extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double 
 
 extern "C" int wcl_grad(wcl_ctx *c, const double *x, const double *y, double *gU, double *gk)
 {
-    (void)x; (void)y; (void)gU; (void)gk;
-    if (!c) return fail(WCL_EINVAL, "null context");
-    return fail(WCL_EINVAL, "wcl_grad: not available in this build");
+    if (!c || !x || !y || !gU || !gk) return fail(WCL_EINVAL, "null argument");
+    if (!c->have_params) return fail(WCL_ESTATE, "wcl_grad before wcl_set_gauge and wcl_set_params");
+    const size_t Vh = c->Vh;
+    const size_t f64 = 2 * spinor_bytes(8, Vh);
+    void *X, *Y, *K, *G, *HX, *CX;
+    CHK(wsget(c, S_GX, f64, &X));
+    CHK(wsget(c, S_GY, f64, &Y));
+    CHK(wsget(c, S_GK, 2 * 6 * 9 * 16 * Vh, &K));
+    CHK(wsget(c, S_GG, link_bytes(8, Vh), &G));
+    CHK(wsget(c, S_GHX, f64, &HX));
+    CHK(wsget(c, S_GCX, f64, &CX));
+    HIPCHK(launch_pack_spinor(c->g, x, X, c->st));
+    HIPCHK(launch_pack_spinor(c->g, y, Y, c->st));
+    HIPCHK(launch_grad(c->g, c->U64, X, Y, K, c->kappa, c->csw, G, c->st));
+    HIPCHK(launch_export_links(c->g, G, gU, c->st));
+    // dL/dkappa = Re<y, H x> + c_sw Re<y, C x>
+    for (int p = 0; p < 2; p++) {
+        HopLaunch L = hop_base(c, P64, P64);
+        L.mode = HOP;
+        L.p = p;
+        L.in = par(X, P64, Vh, 1 - p);
+        L.out = par(HX, P64, Vh, p);
+        CHK(run_hop(c, L));
+    }
+    HIPCHK(launch_sigmaF(c->g, c->U64, X, CX, c->st));
+    const void *a[2] = {Y, Y}, *b[2] = {HX, CX};
+    HIPCHK(launch_dots(P64, 24 * Vh, 2, a, b, c->partials, nullptr, c->st));
+    double part[4 * RED_BLOCKS];
+    HIPCHK(hipMemcpyAsync(part, c->partials, sizeof(part), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double yhx = 0.0, ycx = 0.0;
+    for (int j = 0; j < RED_BLOCKS; j++) {
+        yhx += part[0 * RED_BLOCKS + j];
+        ycx += part[2 * RED_BLOCKS + j];
+    }
+    *gk = yhx + c->csw * ycx;
+    return WCL_OK;
 }
 
 // ===========================================================================

@@ -46,42 +46,104 @@ WCL_D void ext_to_global(const Geom &g, int mu, int b, int a, int delta, int &ti
     x = tile * g.B[mu] + loc;
 }
 
-template <int MU, int S>
-WCL_D void ras_hop_dir(const float2 *src, int Ne, int nidx, float sgn, const cplx<float> u[9], bool dag,
-                       cplx<float> acc[12])
+// One hop of the block operator: the neighbour spinor comes from LDS, the
+// link from global memory; a neighbour outside the extended block is replaced
+// by the site itself with weight 0 (Dirichlet cut without divergent branches).
+struct RasStage {
+    cplx<float> u[9];
+    uint32_t ln;   // local half index of the neighbour (other parity)
+    float w;       // 0 (outside the block), else the t boundary sign
+};
+
+WCL_D void ras_fence(cplx<float> acc[12], uint32_t &a, uint32_t &b)
 {
+    asm volatile(""
+                 : "+v"(acc[0].re), "+v"(acc[0].im), "+v"(acc[1].re), "+v"(acc[1].im), "+v"(acc[2].re),
+                   "+v"(acc[2].im), "+v"(acc[3].re), "+v"(acc[3].im), "+v"(acc[4].re), "+v"(acc[4].im),
+                   "+v"(acc[5].re), "+v"(acc[5].im), "+v"(acc[6].re), "+v"(acc[6].im), "+v"(acc[7].re),
+                   "+v"(acc[7].im), "+v"(acc[8].re), "+v"(acc[8].im), "+v"(acc[9].re), "+v"(acc[9].im),
+                   "+v"(acc[10].re), "+v"(acc[10].im), "+v"(acc[11].re), "+v"(acc[11].im), "+v"(a), "+v"(b));
+}
+
+// nb: packed neighbour table, entry K = forward (K even) / backward (K odd)
+// in direction K/2: the local half index of the other parity, 0xffff if the
+// neighbour is outside the block.  The link of hop K is prefetched (global
+// memory, long latency) one hop ahead; the neighbour spinor is read from LDS
+// when the hop is computed.
+template <typename SL, int K>
+WCL_D void ras_load(const void *links, int q, uint32_t gq, uint32_t Vh, uint32_t t, const uint32_t nb[4],
+                    const int *gnb, float sf, float sb, RasStage &st, cplx<float> acc[12])
+{
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
+    uint32_t ln = (nb[MU] >> (FWD ? 0 : 16)) & 0xffffu;
+    const bool in = ln != 0xffffu;
+    if (!in) ln = t;                       // any valid site; its weight is 0
+    uint32_t gl = FWD ? gq : (uint32_t)gnb[ln];
+    ras_fence(acc, ln, gl);
+    load_link<SL, float>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
+    st.ln = ln;
+    st.w = in ? (MU == 3 ? (FWD ? sf : sb) : 1.f) : 0.f;
+}
+
+template <int K, int NE>
+WCL_D void ras_compute(const RasStage &st, const float2 *src, cplx<float> acc[12])
+{
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
+    constexpr int S = FWD ? -1 : 1;
     cplx<float> psi[12], hh[6], uh[6];
 #pragma unroll
     for (int c = 0; c < 12; c++) {
-        const float2 v = src[c * Ne + nidx];
+        const float2 v = src[c * NE + st.ln];
         psi[c] = {v.x, v.y};
     }
     project<MU, S, float>(psi, hh);
 #pragma unroll
-    for (int k = 0; k < 6; k++) hh[k] = sgn * hh[k];
-    if (dag) su3_dag_mul(u, hh, uh);
-    else su3_mul(u, hh, uh);
+    for (int k = 0; k < 6; k++) hh[k] = st.w * hh[k];
+    if (FWD) su3_mul(st.u, hh, uh);
+    else su3_dag_mul(st.u, hh, uh);
     accumulate<MU, S, float>(acc, uh);
 }
 
-// Hop on one parity q of the extended block, reading the other parity from
-// LDS.  nb[2*mu+0/1] = local half index of the forward / backward neighbour
-// or -1 outside the block; gq = global half index of the site; gnb = global
-// half index table of the other parity.
-template <typename SL, int MU>
-WCL_D void ras_dir(const RasArgs &a, int q, int gq, const int nb[8], const int *gnb, const float2 *src, int Ne,
-                   float sf, float sb, cplx<float> acc[12])
+// acc = (block hop of the other parity, read from src) at this thread's site
+template <typename SL, int NE>
+WCL_D void ras_hop(const void *links, int q, uint32_t gq, uint32_t Vh, uint32_t t, const uint32_t nb[4],
+                   const int *gnb, const float2 *src, float sf, float sb, cplx<float> acc[12])
 {
-    const size_t Vh = a.g.Vh;
-    if (nb[2 * MU] >= 0) {
-        cplx<float> u[9];
-        load_link<SL, float>(a.links, MU, q, gq, Vh, u);
-        ras_hop_dir<MU, -1>(src, Ne, nb[2 * MU], MU == 3 ? sf : 1.0f, u, false, acc);
-    }
-    if (nb[2 * MU + 1] >= 0) {
-        cplx<float> u[9];
-        load_link<SL, float>(a.links, MU, 1 - q, gnb[nb[2 * MU + 1]], Vh, u);
-        ras_hop_dir<MU, 1>(src, Ne, nb[2 * MU + 1], MU == 3 ? sb : 1.0f, u, true, acc);
+    RasStage A, B;
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = {0.f, 0.f};
+    ras_load<SL, 0>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
+    ras_load<SL, 1>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
+    ras_compute<0, NE>(A, src, acc);
+    ras_load<SL, 2>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
+    ras_compute<1, NE>(B, src, acc);
+    ras_load<SL, 3>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
+    ras_compute<2, NE>(A, src, acc);
+    ras_load<SL, 4>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
+    ras_compute<3, NE>(B, src, acc);
+    ras_load<SL, 5>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
+    ras_compute<4, NE>(A, src, acc);
+    ras_load<SL, 6>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
+    ras_compute<5, NE>(B, src, acc);
+    ras_load<SL, 7>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
+    ras_compute<6, NE>(A, src, acc);
+    ras_compute<7, NE>(B, src, acc);
+}
+
+// out = A acc, one chirality block at a time; each block's loads wait for
+// the preceding work (fence), which keeps 36 clover reals live, not 72.
+template <typename SL>
+WCL_D void ras_clover(const void *clov, int q, uint32_t gq, uint32_t Vh, cplx<float> acc[12], cplx<float> out[12])
+{
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+        uint32_t gc = gq, dummy = 0;
+        ras_fence(acc, gc, dummy);
+        float cl[36];
+        load_clover_half<SL, float>(clov, q, gc, Vh, half, cl);
+        clover_mul_half(cl, acc + 6 * half, out + 6 * half);
     }
 }
 
@@ -114,9 +176,10 @@ template <typename SL, int MAXNE>
 __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 {
     if (a.sc && a.sc->done) return;
-    __shared__ float2 sE[12 * MAXNE];
-    __shared__ float2 sO[12 * MAXNE];
-    __shared__ int gh[2 * MAXNE];
+    // component-major with the compile-time stride MAXNE (immediate LDS offsets)
+    __shared__ float2 sE[12 * MAXNE];   // MR residual r on the even block sites
+    __shared__ float2 sO[12 * MAXNE];   // y = A_oo^-1 H_oe r on the odd block sites
+    __shared__ int gh[2 * MAXNE];       // global half index of every block site
     __shared__ double red[4 * 16 + 4];
 
     const Geom &g = a.g;
@@ -134,7 +197,6 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
         bc[3] = r / g.NB[2];
     }
 
-    // global half index of every site of the extended block, both parities
     for (int i = threadIdx.x; i < 2 * Ne; i += blockDim.x) {
         const int q = i >= Ne ? 1 : 0;
         int li = i - q * Ne;
@@ -152,17 +214,17 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             blkid += tile * g.sb[mu];
             lin += loc * g.sl[mu];
         }
-        gh[i] = blkid * g.Hb + (lin >> 1);
+        gh[q * MAXNE + (i - q * Ne)] = blkid * g.Hb + (lin >> 1);
     }
 
-    // the sites of this thread: local half index t on both parities
-    const int t = threadIdx.x;
-    const bool active = t < Ne;
-    int nbE[8], nbO[8];
+    // this thread owns local half index t on both parities
+    const uint32_t t = threadIdx.x;
+    const bool active = (int)t < Ne;
+    uint32_t nbE[4], nbO[4];
     float sfE = 1.f, sbE = 1.f, sfO = 1.f, sbO = 1.f;
     bool core = false;
 #pragma unroll
-    for (int k = 0; k < 8; k++) { nbE[k] = -1; nbO[k] = -1; }
+    for (int k = 0; k < 4; k++) { nbE[k] = 0xffffffffu; nbO[k] = 0xffffffffu; }
     if (active) {
 #pragma unroll
         for (int q = 0; q < 2; q++) {
@@ -176,11 +238,12 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             const int ev[4] = {e0, e1, e2, e3};
             const int lin = a0 + e0 * (a1 + e1 * (a2 + e2 * a3));
             int st = 1;
-            int *nb = q == 0 ? nbE : nbO;
+            uint32_t *nb = q == 0 ? nbE : nbO;
 #pragma unroll
             for (int mu = 0; mu < 4; mu++) {
-                nb[2 * mu] = (av[mu] + 1 < ev[mu]) ? ((lin + st) >> 1) : -1;
-                nb[2 * mu + 1] = (av[mu] >= 1) ? ((lin - st) >> 1) : -1;
+                const uint32_t f = (av[mu] + 1 < ev[mu]) ? (uint32_t)((lin + st) >> 1) : 0xffffu;
+                const uint32_t bk = (av[mu] >= 1) ? (uint32_t)((lin - st) >> 1) : 0xffffu;
+                nb[mu] = f | (bk << 16);
                 st *= ev[mu];
             }
             int tile, loc, xt;
@@ -199,73 +262,73 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
         }
     }
     __syncthreads();
-    const int gE = active ? gh[t] : 0;
-    const int gO = active ? gh[Ne + t] : 0;
-    const size_t Vh = g.Vh;
+    const uint32_t gE = active ? (uint32_t)gh[t] : 0u;
+    const uint32_t gO = active ? (uint32_t)gh[MAXNE + t] : 0u;
+    const uint32_t Vh = g.Vh;
 
-    cplx<float> r[12], z[12];
+    // r = the input on the even block sites (zero start: z = 0, r = rhs)
+    if (active) {
+        cplx<float> r[12];
+        load_spinor<float, float>(a.in, gE, Vh, r);
 #pragma unroll
-    for (int c = 0; c < 12; c++) { r[c] = {0.f, 0.f}; z[c] = {0.f, 0.f}; }
-    if (active) load_spinor<float, float>(a.in, gE, Vh, r);
+        for (int c = 0; c < 12; c++) sE[c * MAXNE + t] = make_float2(r[c].re, r[c].im);
+    }
 
     for (int it = 0; it < a.iters; it++) {
-        if (active) {
-#pragma unroll
-            for (int c = 0; c < 12; c++) sE[c * Ne + t] = make_float2(r[c].re, r[c].im);
-        }
         __syncthreads();
         // odd half: y = A_oo^-1 H_oe r on the odd block sites
         if (active) {
             cplx<float> acc[12], y[12];
+            ras_hop<SL, MAXNE>(a.links, 1, gO, Vh, t, nbO, gh, sE, sfO, sbO, acc);
+            ras_clover<SL>(a.clov_inv, 1, gO, Vh, acc, y);
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = {0.f, 0.f};
-            ras_dir<SL, 0>(a, 1, gO, nbO, gh, sE, Ne, sfO, sbO, acc);
-            ras_dir<SL, 1>(a, 1, gO, nbO, gh, sE, Ne, sfO, sbO, acc);
-            ras_dir<SL, 2>(a, 1, gO, nbO, gh, sE, Ne, sfO, sbO, acc);
-            ras_dir<SL, 3>(a, 1, gO, nbO, gh, sE, Ne, sfO, sbO, acc);
-            float cl[72];
-            load_clover<SL, float>(a.clov_inv, 1, gO, Vh, cl);
-            clover_mul(cl, acc, y);
-#pragma unroll
-            for (int c = 0; c < 12; c++) sO[c * Ne + t] = make_float2(y[c].re, y[c].im);
+            for (int c = 0; c < 12; c++) sO[c * MAXNE + t] = make_float2(y[c].re, y[c].im);
         }
         __syncthreads();
         // even half: q = r - kappa^2 A_ee^-1 H_eo y
         cplx<float> qv[12];
-#pragma unroll
-        for (int c = 0; c < 12; c++) qv[c] = {0.f, 0.f};
         double dots[3] = {0.0, 0.0, 0.0};
         if (active) {
             cplx<float> acc[12], w[12];
-#pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = {0.f, 0.f};
-            ras_dir<SL, 0>(a, 0, gE, nbE, gh + Ne, sO, Ne, sfE, sbE, acc);
-            ras_dir<SL, 1>(a, 0, gE, nbE, gh + Ne, sO, Ne, sfE, sbE, acc);
-            ras_dir<SL, 2>(a, 0, gE, nbE, gh + Ne, sO, Ne, sfE, sbE, acc);
-            ras_dir<SL, 3>(a, 0, gE, nbE, gh + Ne, sO, Ne, sfE, sbE, acc);
-            float cl[72];
-            load_clover<SL, float>(a.clov_inv, 0, gE, Vh, cl);
-            clover_mul(cl, acc, w);
+            ras_hop<SL, MAXNE>(a.links, 0, gE, Vh, t, nbE, gh + MAXNE, sO, sfE, sbE, acc);
+            ras_clover<SL>(a.clov_inv, 0, gE, Vh, acc, w);
             float qr = 0.f, qi = 0.f, qq = 0.f;
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                qv[c] = {fmaf(-a.kappa2, w[c].re, r[c].re), fmaf(-a.kappa2, w[c].im, r[c].im)};
-                qr += qv[c].re * r[c].re + qv[c].im * r[c].im;
-                qi += qv[c].re * r[c].im - qv[c].im * r[c].re;
+                const float2 r = sE[c * MAXNE + t];
+                qv[c] = {fmaf(-a.kappa2, w[c].re, r.x), fmaf(-a.kappa2, w[c].im, r.y)};
+                qr += qv[c].re * r.x + qv[c].im * r.y;
+                qi += qv[c].re * r.y - qv[c].im * r.x;
                 qq += qv[c].re * qv[c].re + qv[c].im * qv[c].im;
             }
             dots[0] = qr; dots[1] = qi; dots[2] = qq;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; c++) qv[c] = {0.f, 0.f};
         }
         block_allreduce<3>(dots, red);
         if (dots[2] == 0.0) break;
         const float ar = (float)(dots[0] / dots[2]), ai = (float)(dots[1] / dots[2]);
+        if (active) {
+            // z += alpha r (kept only where it is written: the core), r -= alpha q
+            cplx<float> z[12];
+            if (core) {
+                if (it == 0) {
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            z[c] = {z[c].re + ar * r[c].re - ai * r[c].im, z[c].im + ar * r[c].im + ai * r[c].re};
-            r[c] = {r[c].re - (ar * qv[c].re - ai * qv[c].im), r[c].im - (ar * qv[c].im + ai * qv[c].re)};
+                    for (int c = 0; c < 12; c++) z[c] = {0.f, 0.f};
+                } else {
+                    load_spinor<float, float>(a.out, gE, Vh, z);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const float2 r = sE[c * MAXNE + t];
+                if (core) z[c] = {z[c].re + ar * r.x - ai * r.y, z[c].im + ar * r.y + ai * r.x};
+                sE[c * MAXNE + t] = make_float2(r.x - (ar * qv[c].re - ai * qv[c].im), r.y - (ar * qv[c].im + ai * qv[c].re));
+            }
+            if (core) store_spinor<float, float>(a.out, gE, Vh, z);
         }
     }
-    if (active && core) store_spinor<float, float>(a.out, gE, Vh, z);
 }
 
 int ras_threads(const Geom &g, int overlap)

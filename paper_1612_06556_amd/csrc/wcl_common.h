@@ -423,6 +423,58 @@ WCL_D void store_clover(void *base, int p, uint32_t h, uint32_t Vh, const double
     }
 }
 
+// One chirality block (36 reals) of a clover site: half 0 = spins 0,1,
+// half 1 = spins 2,3.
+template <typename S, typename R>
+WCL_D void load_clover_half(const void *base, int p, uint32_t h, uint32_t Vh, int half, R c[36])
+{
+    if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (uint32_t k = 0; k < 18; k++) {
+            const double2 d = ldf<double2>(base, (((uint32_t)p * 36 + 18 * half + k) * Vh + h) * 16u);
+            c[2 * k] = (R)d.x;
+            c[2 * k + 1] = (R)d.y;
+        }
+    } else if constexpr (sizeof(S) == 4) {
+#pragma unroll
+        for (uint32_t k = 0; k < 9; k++) {
+            const float4 f = ldf<float4>(base, (((uint32_t)p * 18 + 9 * half + k) * Vh + h) * 16u);
+            c[4 * k] = f.x; c[4 * k + 1] = f.y; c[4 * k + 2] = f.z; c[4 * k + 3] = f.w;
+        }
+    } else {
+        // 36 halves starting at half 36*half: uint4 words w0 .. w0+4 (8 halves each)
+        float t[40];
+        const uint32_t w0 = half ? 4u : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 5; k++) {
+            const uint4 w = ldf<uint4>(base, (((uint32_t)p * 9 + w0 + k) * Vh + h) * 16u);
+            float2 a = h2f2(w.x), b = h2f2(w.y), cc = h2f2(w.z), d = h2f2(w.w);
+            t[8 * k + 0] = a.x; t[8 * k + 1] = a.y; t[8 * k + 2] = b.x; t[8 * k + 3] = b.y;
+            t[8 * k + 4] = cc.x; t[8 * k + 5] = cc.y; t[8 * k + 6] = d.x; t[8 * k + 7] = d.y;
+        }
+        const int off = half ? 4 : 0;
+#pragma unroll
+        for (int k = 0; k < 36; k++) c[k] = (R)t[off + k];
+    }
+}
+
+template <typename R>
+WCL_D void clover_mul_half(const R blk[36], const cplx<R> x[6], cplx<R> y[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = blk[i] * x[i];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i + 1; j < 6; j++) {
+            const cplx<R> a = {blk[6 + 2 * k], blk[7 + 2 * k]};
+            y[i] = cfma(a, x[j], y[i]);
+            y[j] = cjfma(a, x[i], y[j]);
+            k++;
+        }
+}
+
 // out = A v for a packed Hermitian clover site (two 6x6 blocks): 504 flop.
 template <typename R>
 WCL_D void clover_mul(const R c[72], const cplx<R> v[12], cplx<R> out[12])

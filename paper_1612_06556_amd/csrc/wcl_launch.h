@@ -137,6 +137,15 @@ struct RasLaunch {
     const Scalars *sc;   // may be null; skips when sc->done
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
+
+// Gradient (FP64): K field [2][6][9][Vh] double2 scratch, G = link field.
+hipError_t launch_grad(const Geom &g, const void *u64, const void *X, const void *Y, void *K, double kappa,
+                       double csw, void *G, hipStream_t st);
+// out = sum_{mu<nu} sigma_{mu nu} F_{mu nu} X (both parities, FP64, from the links)
+hipError_t launch_sigmaF(const Geom &g, const void *u64, const void *X, void *out, hipStream_t st);
+hipError_t launch_export_links(const Geom &g, const void *G, double *canon, hipStream_t st);
+// gamma5 on nsec FP64 e/o sections of Vh sites (in place)
+hipError_t launch_gamma5(size_t nsec, size_t Vh, void *f, hipStream_t st);
 int ras_threads(const Geom &g, int overlap);
 
 }  // namespace wcl
