@@ -62,9 +62,10 @@ struct wcl_ctx {
     bool have_gauge = false, have_params = false;
     int ras_overlap = 1, ras_iters = 4;
     std::vector<Buf> ws;        // workspace, indexed by slot
-    double *partials = nullptr; // [6][RED_BLOCKS]
-    Scalars *sc = nullptr;      // [2]: outer, inner
+    double *partials = nullptr; // [cap][6][RED_BLOCKS]
+    Scalars *sc = nullptr;      // [3][cap]: outer, inner, final/scratch scalars per right-hand side
     Scalars *sc_host = nullptr; // pinned mirror
+    int cap = 0;                // right-hand sides the scalar and partial buffers hold
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
     int hop_block = 256, hop_depth = 2, hop_xcd = 1;
     // event profiling of kernel classes
@@ -181,17 +182,24 @@ int run_ras(wcl_ctx *c, const RasLaunch &R)
     return profiled(c, WCL_K_RAS, b, f, [&] { return launch_ras(R, c->st); });
 }
 
-int run_clover(wcl_ctx *c, int lp, int sp, int p, const void *clov, const void *in, void *out)
+int run_clover(wcl_ctx *c, int lp, int sp, int p, const void *clov, const void *in, void *out, int nrhs = 1,
+               size_t in_stride = 0, size_t out_stride = 0)
 {
     const double sb = sp == P64 ? 192.0 : sp == P32 ? 96.0 : 48.0;
     const double cb = lp == P64 ? 576.0 : lp == P32 ? 288.0 : 144.0;
-    return profiled(c, WCL_K_CLOVER, (2 * sb + cb) * c->Vh, 504.0 * c->Vh,
-                    [&] { return launch_clover(c->g, lp, sp, p, clov, in, out, c->st); });
+    return profiled(c, WCL_K_CLOVER, (2 * sb * nrhs + cb) * c->Vh, 504.0 * c->Vh * nrhs, [&] {
+        return launch_clover(c->g, lp, sp, p, clov, in, out, c->st, nrhs, in_stride, out_stride);
+    });
 }
+
+// Byte strides of batched fields: an even (or odd) vector per right-hand
+// side, and a full field (both parities) per right-hand side.
+size_t half_bytes(int prec, size_t Vh) { return spinor_bytes(prec_bytes(prec), Vh); }
+size_t full_bytes(int prec, size_t Vh) { return 2 * spinor_bytes(prec_bytes(prec), Vh); }
 
 // One parity of the full operator: out_p = A_pp x_p + coef H in_{1-p}
 int full_D_parity(wcl_ctx *c, int lprec, int sprec, int p, const void *field_in, void *field_out, int dagger,
-                  const Scalars *sc)
+                  const Scalars *sc, int nrhs)
 {
     HopLaunch L = hop_base(c, lprec, sprec);
     L.mode = CLOVX;
@@ -203,23 +211,29 @@ int full_D_parity(wcl_ctx *c, int lprec, int sprec, int p, const void *field_in,
     L.clov = clov_for(c, lprec);
     L.coef = -c->kappa;
     L.sc = sc;
+    L.nrhs = nrhs;
+    L.in_stride = L.out_stride = L.x_stride = full_bytes(sprec, c->Vh);
     CHK(run_hop(c, L));
     return WCL_OK;
 }
 
-int full_D(wcl_ctx *c, int lprec, int sprec, const void *in, void *out, int dagger, const Scalars *sc = nullptr)
+int full_D(wcl_ctx *c, int lprec, int sprec, const void *in, void *out, int dagger, const Scalars *sc = nullptr,
+           int nrhs = 1)
 {
-    CHK(full_D_parity(c, lprec, sprec, 0, in, out, dagger, sc));
-    CHK(full_D_parity(c, lprec, sprec, 1, in, out, dagger, sc));
+    CHK(full_D_parity(c, lprec, sprec, 0, in, out, dagger, sc, nrhs));
+    CHK(full_D_parity(c, lprec, sprec, 1, in, out, dagger, sc, nrhs));
     return WCL_OK;
 }
 
 // Schur operator on even fields: tmp_o = A_oo^-1 H_oe in_e ; out_e = in_e - k^2 A_ee^-1 H_eo tmp_o
-int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc)
+int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc,
+          int nrhs = 1)
 {
     HopLaunch L = hop_base(c, lprec, sprec);
     L.clov = clovinv_for(c, lprec);
     L.sc = sc;
+    L.nrhs = nrhs;
+    L.in_stride = L.out_stride = L.x_stride = half_bytes(sprec, c->Vh);
     L.mode = CLOV_H;
     L.p = 1;
     L.in = in_e;
@@ -235,11 +249,12 @@ int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void 
     return WCL_OK;
 }
 
-// bhat_e = A_ee^-1 (b_e + k H_eo A_oo^-1 b_o)  (field b: both parities, FP64)
-int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_e)
+// bhat_e = A_ee^-1 (b_e + k H_eo A_oo^-1 b_o)  (b: full FP64 fields, bhat, tmp: even/odd FP64 vectors)
+int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_e, int nrhs = 1)
 {
-    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o));
-    CHK(run_clover(c, P64, P64, 0, c->Ti64, par(b, P64, c->Vh, 0), tmp_e));
+    const size_t fb = full_bytes(P64, c->Vh), hb = half_bytes(P64, c->Vh);
+    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o, nrhs, fb, hb));
+    CHK(run_clover(c, P64, P64, 0, c->Ti64, par(b, P64, c->Vh, 0), tmp_e, nrhs, fb, hb));
     HopLaunch L = hop_base(c, P64, P64);
     L.mode = XPAY;
     L.p = 0;
@@ -248,14 +263,17 @@ int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_
     L.out = bhat_e;
     L.clov = c->Ti64;
     L.coef = c->kappa;
+    L.nrhs = nrhs;
+    L.in_stride = L.out_stride = L.x_stride = hb;
     CHK(run_hop(c, L));
     return WCL_OK;
 }
 
-// x_o = A_oo^-1 (b_o + k H_oe x_e) into the odd half of field x (even half = x_e already)
-int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o)
+// x_o = A_oo^-1 (b_o + k H_oe x_e) into the odd half of the full fields x (even half = x_e already)
+int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o, int nrhs = 1)
 {
-    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o));
+    const size_t fb = full_bytes(P64, c->Vh), hb = half_bytes(P64, c->Vh);
+    CHK(run_clover(c, P64, P64, 1, c->Ti64, par(b, P64, c->Vh, 1), tmp_o, nrhs, fb, hb));
     HopLaunch L = hop_base(c, P64, P64);
     L.mode = XPAY;
     L.p = 1;
@@ -264,39 +282,70 @@ int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o)
     L.out = par(x, P64, c->Vh, 1);
     L.clov = c->Ti64;
     L.coef = c->kappa;
+    L.nrhs = nrhs;
+    L.in_stride = L.out_stride = fb;
+    L.x_stride = hb;
     CHK(run_hop(c, L));
     return WCL_OK;
 }
 
 int check_prec(int prec) { return (prec == 64 || prec == 32 || prec == 16) ? WCL_OK : fail(WCL_EINVAL, "prec must be 64, 32 or 16"); }
 
-int read_scalars(wcl_ctx *c, int which)
+// Scalar and partial buffers for n right-hand sides: outer scalars at
+// sc[0, n), inner at sc[cap, cap + n), per-rhs flags/scratch at sc[2 cap, ...).
+int ensure_batch(wcl_ctx *c, int n)
 {
-    HIPCHK(hipMemcpyAsync(c->sc_host + which, c->sc + which, sizeof(Scalars), hipMemcpyDeviceToHost, c->st));
+    if (n <= c->cap) return WCL_OK;
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (c->sc) (void)hipFree(c->sc);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    c->sc = nullptr; c->partials = nullptr; c->sc_host = nullptr; c->cap = 0;
+    CHK(alloc((void **)&c->sc, sizeof(Scalars) * 3 * n));
+    CHK(alloc((void **)&c->partials, sizeof(double) * 6 * RED_BLOCKS * n));
+    if (hipHostMalloc((void **)&c->sc_host, sizeof(Scalars) * 3 * n, hipHostMallocDefault) != hipSuccess)
+        return fail(WCL_ENOMEM, "hipHostMalloc failed");
+    memset(c->sc_host, 0, sizeof(Scalars) * 3 * n);
+    HIPCHK(hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars) * 3 * n, hipMemcpyHostToDevice, c->st));
+    c->cap = n;
+    return WCL_OK;
+}
+
+Scalars *SO(wcl_ctx *c) { return c->sc; }
+Scalars *SI(wcl_ctx *c) { return c->sc + c->cap; }
+Scalars *SF(wcl_ctx *c) { return c->sc + 2 * c->cap; }
+Scalars *HO(wcl_ctx *c) { return c->sc_host; }
+Scalars *HI(wcl_ctx *c) { return c->sc_host + c->cap; }
+Scalars *HF(wcl_ctx *c) { return c->sc_host + 2 * c->cap; }
+
+int read_sc(wcl_ctx *c, Scalars *host, const Scalars *dev, int n)
+{
+    HIPCHK(hipMemcpyAsync(host, dev, sizeof(Scalars) * n, hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     return WCL_OK;
 }
 
-int write_scalars(wcl_ctx *c, int which)
+int write_sc(wcl_ctx *c, Scalars *dev, const Scalars *host, int n)
 {
-    HIPCHK(hipMemcpyAsync(c->sc + which, c->sc_host + which, sizeof(Scalars), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(dev, host, sizeof(Scalars) * n, hipMemcpyHostToDevice, c->st));
     return WCL_OK;
 }
 
-// |v|^2 of n complex numbers into sc[which].t[0] (device)
-int norm2_dev(wcl_ctx *c, int prec, size_t n, const void *v, int which)
+// |v_k|^2 of n right-hand sides (m complex numbers each, `stride` apart) into dst[k].t[0]
+int norms_dev(wcl_ctx *c, int prec, size_t m, const void *v, size_t stride, int n, Scalars *dst)
 {
     const void *a[1] = {v}, *b[1] = {v};
-    HIPCHK(launch_dots(prec, n, 1, a, b, c->partials, nullptr, c->st));
-    HIPCHK(launch_finalize(NORM_ONLY, 2, c->partials, c->sc + which, c->st));
+    HIPCHK(launch_dots(prec, m, 1, a, b, c->partials, nullptr, c->st, n, stride));
+    HIPCHK(launch_finalize(NORM_ONLY, 2, c->partials, dst, c->st, n));
     return WCL_OK;
 }
 
-int norm2_host(wcl_ctx *c, int prec, size_t n, const void *v, double *out)
+// host copies of |v_k|^2 (uses the scratch scalars' t[0])
+int norms_host(wcl_ctx *c, int prec, size_t m, const void *v, size_t stride, int n, double *out)
 {
-    CHK(norm2_dev(c, prec, n, v, 1));
-    CHK(read_scalars(c, 1));
-    *out = c->sc_host[1].t[0];
+    CHK(norms_dev(c, prec, m, v, stride, n, SF(c)));
+    CHK(read_sc(c, HF(c), SF(c), n));
+    for (int k = 0; k < n; k++) out[k] = HF(c)[k].t[0];
     return WCL_OK;
 }
 
@@ -368,17 +417,10 @@ int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream,
         return fail(WCL_EHIP, "no HIP device");
     }
     int rc = WCL_OK;
-    if ((rc = alloc((void **)&c->partials, sizeof(double) * 6 * RED_BLOCKS)) != WCL_OK ||
-        (rc = alloc((void **)&c->sc, sizeof(Scalars) * 2)) != WCL_OK ||
-        (rc = alloc((void **)&c->info, sizeof(int))) != WCL_OK) {
+    if ((rc = alloc((void **)&c->info, sizeof(int))) != WCL_OK || (rc = ensure_batch(c, 1)) != WCL_OK) {
         wcl_destroy(c);
         return rc;
     }
-    if (hipHostMalloc((void **)&c->sc_host, sizeof(Scalars) * 2, hipHostMallocDefault) != hipSuccess) {
-        wcl_destroy(c);
-        return fail(WCL_ENOMEM, "hipHostMalloc failed");
-    }
-    memset(c->sc_host, 0, sizeof(Scalars) * 2);
     *out = c;
     return WCL_OK;
 }
@@ -574,30 +616,36 @@ void wcl_default_opts(wcl_solve_opts *o)
 }  // extern "C"
 
 // ===========================================================================
-// Solvers.
+// Solvers (all right-hand sides of a call advance in lockstep; every vector
+// carries a right-hand-side dimension and every BiCGStab scalar is per rhs;
+// a converged right-hand side is masked out of every kernel by its scalars).
 namespace {
 
 struct SolveWs {
-    // FP64 full fields (both parities)
+    int n;
+    // FP64 full fields [n][2][12][Vh]
     void *b, *x, *res;
-    // FP64 even vectors
-    void *bh, *xe, *r, *rt, *p, *v, *s, *t, *ph, *sh, *o;
-    // FP32 even vectors
+    // FP64 even vectors [n][12][Vh]
+    void *bh, *xe, *r, *rt, *p, *v, *s, *t, *ph, *sh, *o, *o2;
+    // FP32 even vectors [n][6][Vh] float4
     void *rhs, *x32, *r32, *rt32, *p32, *v32, *s32, *t32, *ph32, *sh32, *o32;
 };
 
-int get_ws(wcl_ctx *c, SolveWs &w, bool inner)
+int get_ws(wcl_ctx *c, SolveWs &w, bool inner, bool plain, int n)
 {
     const size_t Vh = c->Vh;
-    const size_t e64 = spinor_bytes(8, Vh), e32 = spinor_bytes(4, Vh);
+    const size_t e64 = spinor_bytes(8, Vh) * n, e32 = spinor_bytes(4, Vh) * n;
+    w.n = n;
     CHK(wsget(c, S_B64, 2 * e64, &w.b));
     CHK(wsget(c, S_X64, 2 * e64, &w.x));
     CHK(wsget(c, S_R64F, 2 * e64, &w.res));
-    void **ev[] = {&w.bh, &w.xe, &w.r, &w.rt, &w.p, &w.v, &w.s, &w.t, &w.ph, &w.sh, &w.o};
-    for (int k = 0; k < 11; k++) CHK(wsget(c, S_BH + k, e64, ev[k]));
+    // plain FP64 BiCGStab works on full fields: its vectors are twice as long
+    const size_t ev = plain ? 2 * e64 : e64;
+    void **v64[] = {&w.bh, &w.xe, &w.r, &w.rt, &w.p, &w.v, &w.s, &w.t, &w.ph, &w.sh, &w.o, &w.o2};
+    for (int k = 0; k < 12; k++) CHK(wsget(c, S_BH + k, ev, v64[k]));
     if (inner) {
-        void **fv[] = {&w.rhs, &w.x32, &w.r32, &w.rt32, &w.p32, &w.v32, &w.s32, &w.t32, &w.ph32, &w.sh32, &w.o32};
-        for (int k = 0; k < 11; k++) CHK(wsget(c, S_RHS32 + k, e32, fv[k]));
+        void **v32[] = {&w.rhs, &w.x32, &w.r32, &w.rt32, &w.p32, &w.v32, &w.s32, &w.t32, &w.ph32, &w.sh32, &w.o32};
+        for (int k = 0; k < 11; k++) CHK(wsget(c, S_RHS32 + k, e32, v32[k]));
     }
     return WCL_OK;
 }
@@ -611,12 +659,12 @@ struct InnerCfg {
 };
 
 // One BiCGStab iteration (right preconditioned by RAS when enabled) on the
-// FP32 Schur system, all scalars in sc (device).
-int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc)
+// FP32 Schur system for n right-hand sides, scalars sc[0, n) on the device.
+int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, int n)
 {
-    const size_t n = 12 * (size_t)c->Vh;
+    const size_t m = 12 * (size_t)c->Vh;   // complex numbers per right-hand side
     const int lp = cfg.lprec;
-    HIPCHK(launch_bicg_p(P32, n, w.r32, w.p32, w.v32, sc, c->st));
+    HIPCHK(launch_bicg_p(P32, m, w.r32, w.p32, w.v32, sc, c->st, n, m));
     void *ph = w.p32, *sh = w.s32;
     RasLaunch R;
     if (cfg.ras) {
@@ -628,310 +676,336 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc)
         R.clov_inv = clovinv_for(c, lp);
         R.kappa2 = (float)(c->kappa * c->kappa);
         R.sc = sc;
+        R.nrhs = n;
+        R.stride = half_bytes(P32, c->Vh);
         R.in = w.p32;
         R.out = w.ph32;
         CHK(run_ras(c, R));
         ph = w.ph32;
     }
-    CHK(schur(c, lp, P32, ph, w.v32, w.o32, sc));
+    CHK(schur(c, lp, P32, ph, w.v32, w.o32, sc, n));
     {
         const void *a[1] = {w.rt32}, *b[1] = {w.v32};
-        HIPCHK(launch_dots(P32, n, 1, a, b, c->partials, sc, c->st));
-        HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st));
+        HIPCHK(launch_dots(P32, m, 1, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n));
     }
-    HIPCHK(launch_bicg_s(P32, n, w.r32, w.v32, w.s32, sc, c->st));
+    HIPCHK(launch_bicg_s(P32, m, w.r32, w.v32, w.s32, sc, c->st, n, m));
     if (cfg.ras) {
         R.in = w.s32;
         R.out = w.sh32;
         CHK(run_ras(c, R));
         sh = w.sh32;
     }
-    CHK(schur(c, lp, P32, sh, w.t32, w.o32, sc));
+    CHK(schur(c, lp, P32, sh, w.t32, w.o32, sc, n));
     {
         const void *a[2] = {w.t32, w.t32}, *b[2] = {w.s32, w.t32};
-        HIPCHK(launch_dots(P32, n, 2, a, b, c->partials, sc, c->st));
-        HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st));
+        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n));
     }
-    HIPCHK(launch_bicg_xr(P32, n, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st));
+    HIPCHK(launch_bicg_xr(P32, m, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st, n, m));
     {
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(P32, n, 2, a, b, c->partials, sc, c->st));
-        HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st));
+        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n));
     }
     return WCL_OK;
 }
 
-// out64 = ||in64|| * K(in64 / ||in64||): the single-precision inner solve.
-int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, void *out64, int *iters)
+// out64_k = ||in64_k|| * K(in64_k / ||in64_k||) for every right-hand side k
+// whose gate (per-rhs "final" flag) is not set: the single-precision inner
+// solve, all right-hand sides in one set of launches.
+int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, void *out64, int n,
+                std::vector<int> &iters)
 {
-    const size_t n = 12 * (size_t)c->Vh;
+    const size_t m = 12 * (size_t)c->Vh;
     const size_t Vh = c->Vh;
-    Scalars *sc = c->sc + 1;
-    CHK(norm2_dev(c, P64, n, in64, 1));
-    HIPCHK(launch_convert(P64, P32, Vh, Vh, Vh, in64, w.r32, &sc->t[0], 1, 1.0, c->st));
-    HIPCHK(launch_copy(P32, n, w.r32, w.rt32, c->st));
-    HIPCHK(launch_zero(P32, n, w.x32, c->st));
-    HIPCHK(launch_zero(P32, n, w.p32, c->st));
-    HIPCHK(launch_zero(P32, n, w.v32, c->st));
+    Scalars *sc = SI(c);
+    const int sstride = (int)(sizeof(Scalars) / sizeof(double));
+    CHK(norms_dev(c, P64, m, in64, m, n, sc));
+    HIPCHK(launch_convert(P64, P32, n * Vh, Vh, Vh, in64, w.r32, &sc->t[0], 1, 1.0, c->st, 1, sstride));
+    HIPCHK(launch_copy(P32, n * m, w.r32, w.rt32, c->st));
+    HIPCHK(launch_zero(P32, n * m, w.x32, c->st));
+    HIPCHK(launch_zero(P32, n * m, w.p32, c->st));
+    HIPCHK(launch_zero(P32, n * m, w.v32, c->st));
     {
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(P32, n, 2, a, b, c->partials, nullptr, c->st));
-        HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st));
+        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, nullptr, c->st, n, m));
+        HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st, n, SF(c)));
     }
     // Iterations are queued in chunks; every kernel of an iteration queued
-    // after convergence is a no-op.  The chunk length follows the observed
-    // convergence rate so that few such iterations are queued.
+    // after a right-hand side converged is a no-op for it.  The chunk length
+    // follows the observed convergence rate of the slowest right-hand side.
     int launched = 0;
     int chunk = std::min(cfg.check_every, 4);
-    double r2_prev = 1.0;  // |r0|^2 of the normalised right-hand side
-    int it_prev = 0;
+    std::vector<double> r2_prev(n, 1.0);
+    std::vector<int> it_prev(n, 0);
     std::vector<size_t> rec_mark;  // profile records at the start of each queued iteration
+    Scalars *h = HI(c);
     while (launched < cfg.maxit) {
         chunk = std::max(1, std::min(chunk, cfg.maxit - launched));
         for (int k = 0; k < chunk; k++) {
             rec_mark.push_back(c->recs.size());
-            CHK(inner_iteration(c, cfg, w, sc));
+            CHK(inner_iteration(c, cfg, w, sc, n));
         }
         launched += chunk;
-        CHK(read_scalars(c, 1));
-        const Scalars &h = c->sc_host[1];
-        if (h.done) break;
-        // predicted iterations to reach the target at the rate seen so far
-        const int di = h.iter - it_prev;
-        if (di > 0 && h.r2 > 0.0 && h.r2 < r2_prev) {
-            const double rate = std::log(h.r2 / r2_prev) / di;
-            const double need = std::log(h.stop2 * h.b2 / h.r2) / rate;
-            chunk = (int)std::min(16.0, std::max(1.0, std::floor(need)));
-        } else {
-            chunk = std::min(cfg.check_every, 4);
+        CHK(read_sc(c, h, sc, n));
+        bool all = true;
+        double need_max = 0.0;
+        for (int k = 0; k < n; k++) {
+            if (h[k].done) continue;
+            all = false;
+            const int di = h[k].iter - it_prev[k];
+            double need = 4.0;
+            if (di > 0 && h[k].r2 > 0.0 && h[k].r2 < r2_prev[k]) {
+                const double rate = std::log(h[k].r2 / r2_prev[k]) / di;
+                need = std::log(h[k].stop2 * h[k].b2 / h[k].r2) / rate;
+            }
+            need_max = std::max(need_max, need);
+            r2_prev[k] = h[k].r2;
+            it_prev[k] = h[k].iter;
         }
-        r2_prev = h.r2;
-        it_prev = h.iter;
+        if (all) break;
+        chunk = (int)std::min(16.0, std::max(1.0, std::floor(need_max)));
     }
-    *iters = c->sc_host[1].iter;
-    // launches of iterations past the converged one did no work
-    for (size_t k = (size_t)*iters; k < rec_mark.size(); k++) {
-        const size_t end = (k + 1 < rec_mark.size()) ? rec_mark[k + 1] : c->recs.size();
-        for (size_t r = rec_mark[k]; r < end; r++) c->recs[r].bytes = c->recs[r].flops = 0.0;
+    int max_it = 0;
+    for (int k = 0; k < n; k++) {
+        iters[k] = h[k].iter;
+        max_it = std::max(max_it, h[k].iter);
     }
-    HIPCHK(launch_convert(P32, P64, Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st));
+    // work of launches after every right-hand side had converged is void
+    // (with several right-hand sides the per-rhs masking is not separated)
+    for (size_t q = (size_t)max_it; q < rec_mark.size(); q++) {
+        const size_t end = (q + 1 < rec_mark.size()) ? rec_mark[q + 1] : c->recs.size();
+        for (size_t r = rec_mark[q]; r < end; r++) c->recs[r].bytes = c->recs[r].flops = 0.0;
+    }
+    HIPCHK(launch_convert(P32, P64, n * Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st, 1, sstride));
     return WCL_OK;
 }
 
-// true relative residual of the full system: ||b - D x|| / ||b|| (FP64)
-int true_residual(wcl_ctx *c, SolveWs &w, double bnorm2, double *rel)
+// true relative residuals of the full systems: ||b_k - D x_k|| / ||b_k|| (FP64)
+int true_residuals(wcl_ctx *c, SolveWs &w, const std::vector<double> &bnorm2, std::vector<double> &rel)
 {
-    const size_t n = 24 * (size_t)c->Vh;
-    CHK(full_D(c, P64, P64, w.x, w.res, 0));
-    HIPCHK(launch_axpby(P64, n, make_double2(1.0, 0.0), w.b, make_double2(-1.0, 0.0), w.res, c->st));
-    double r2;
-    CHK(norm2_host(c, P64, n, w.res, &r2));
-    *rel = std::sqrt(r2 / bnorm2);
+    const size_t mf = 24 * (size_t)c->Vh;
+    const int n = w.n;
+    CHK(full_D(c, P64, P64, w.x, w.res, 0, nullptr, n));
+    HIPCHK(launch_axpby(P64, n * mf, make_double2(1.0, 0.0), w.b, make_double2(-1.0, 0.0), w.res, c->st));
+    std::vector<double> r2(n);
+    CHK(norms_host(c, P64, mf, w.res, mf, n, r2.data()));
+    for (int k = 0; k < n; k++) rel[k] = bnorm2[k] > 0.0 ? std::sqrt(r2[k] / bnorm2[k]) : 0.0;
     return WCL_OK;
 }
 
-int set_outer_stop(wcl_ctx *c, double stop2)
+// set the "final" flags (gate of the inner solve and mask of the outer)
+int write_final(wcl_ctx *c, const std::vector<int> &final_)
 {
-    CHK(read_scalars(c, 0));
-    c->sc_host[0].stop2 = stop2;
-    c->sc_host[0].done = 0;
-    CHK(write_scalars(c, 0));
+    for (int k = 0; k < (int)final_.size(); k++) HF(c)[k].done = final_[k];
+    CHK(write_sc(c, SF(c), HF(c), (int)final_.size()));
     return WCL_OK;
 }
 
-// FP64 (flexible) BiCGStab on the Schur system with preconditioner K.
-int outer_fbicgstab(wcl_ctx *c, const wcl_solve_opts &o, const InnerCfg &cfg, SolveWs &w, double bnorm2,
-                    wcl_solve_info &info)
+// Generic BiCGStab driver for n right-hand sides in FP64 (right
+// preconditioned by K when given):
+//   PLAIN  : A = full D on full fields, no K, x = w.x, rhs = w.b
+//   FLEX   : A = Dhat on even vectors, K = inner solve, x = w.xe, rhs = w.bh
+// Stops a right-hand side when its true residual of the full system is
+// <= tol; a right-hand side whose recursive residual reached the threshold
+// (or broke down) without a true residual <= tol gets its residual replaced
+// by the true one and its recurrence restarted.
+struct Driver {
+    bool flex;
+    size_t m;       // complex numbers per right-hand side
+    void *x, *bvec;
+};
+
+int apply_A(wcl_ctx *c, const Driver &d, SolveWs &w, const void *in, void *out, const Scalars *sc)
 {
-    const size_t n = 12 * (size_t)c->Vh;
-    Scalars *sc = c->sc;
-    double bh2;
-    CHK(norm2_host(c, P64, n, w.bh, &bh2));
-    HIPCHK(launch_copy(P64, n, w.bh, w.r, c->st));
-    HIPCHK(launch_zero(P64, n, w.xe, c->st));
-    int inner_total = 0;
-    int status = WCL_ENOCONV;
-    for (int restart = 0; restart < 8 && status == WCL_ENOCONV; restart++) {
-        // (re)start the recurrence from the current residual r
-        HIPCHK(launch_copy(P64, n, w.r, w.rt, c->st));
-        HIPCHK(launch_zero(P64, n, w.p, c->st));
-        HIPCHK(launch_zero(P64, n, w.v, c->st));
-        {
-            const void *a[2] = {w.rt, w.r}, *b[2] = {w.r, w.r};
-            HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, nullptr, c->st));
-            HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st));
-        }
-        CHK(read_scalars(c, 0));
+    if (d.flex) return schur(c, P64, P64, in, out, w.o, sc, w.n);
+    return full_D(c, P64, P64, in, out, 0, sc, w.n);
+}
+
+// true residuals; for FLEX the full solution is reconstructed first
+int check_true(wcl_ctx *c, const Driver &d, SolveWs &w, const std::vector<double> &bnorm2, std::vector<double> &rel)
+{
+    if (d.flex) {
+        HIPCHK(launch_zero(P64, w.n * 24 * (size_t)c->Vh, w.x, c->st));
+        // copy x_e into the even halves of the full fields
+        for (int k = 0; k < w.n; k++)
+            HIPCHK(hipMemcpyAsync((char *)w.x + k * full_bytes(P64, c->Vh), (char *)w.xe + k * half_bytes(P64, c->Vh),
+                                  half_bytes(P64, c->Vh), hipMemcpyDeviceToDevice, c->st));
+        CHK(reconstruct64(c, w.b, w.x, w.o, w.n));
+    }
+    return true_residuals(c, w, bnorm2, rel);
+}
+
+// (re)start the recurrence of right-hand side k (or all with k < 0) from r
+int restart(wcl_ctx *c, const Driver &d, SolveWs &w, int k, double tol, const std::vector<double> &bnorm2)
+{
+    const int n = w.n;
+    const int k0 = k < 0 ? 0 : k, cnt = k < 0 ? n : 1;
+    const size_t off = (size_t)k0 * d.m * 16;
+    HIPCHK(launch_copy(P64, cnt * d.m, (char *)w.r + off, (char *)w.rt + off, c->st));
+    HIPCHK(launch_zero(P64, cnt * d.m, (char *)w.p + off, c->st));
+    HIPCHK(launch_zero(P64, cnt * d.m, (char *)w.v + off, c->st));
+    const void *a[2] = {(char *)w.rt + off, (char *)w.r + off}, *b[2] = {(char *)w.r + off, (char *)w.r + off};
+    HIPCHK(launch_dots(P64, d.m, 2, a, b, c->partials, nullptr, c->st, cnt, d.m));
+    HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, SO(c) + k0, c->st, cnt, SF(c) + k0));
+    CHK(read_sc(c, HO(c) + k0, SO(c) + k0, cnt));
+    for (int j = k0; j < k0 + cnt; j++) {
+        Scalars &h = HO(c)[j];
         // stop when |r|^2 <= tol^2 |b|^2 (b2 holds |r0|^2 after the init)
-        const double r02 = c->sc_host[0].b2;
-        if (r02 == 0.0) { status = WCL_OK; break; }
-        CHK(set_outer_stop(c, o.tol * o.tol * bnorm2 / r02));
-        bool restart_now = false;
-        while (info.outer_iters < o.max_outer) {
-            HIPCHK(launch_bicg_p(P64, n, w.r, w.p, w.v, sc, c->st));
-            int it;
-            CHK(inner_solve(c, cfg, w, w.p, w.ph, &it));
-            inner_total += it;
-            CHK(schur(c, P64, P64, w.ph, w.v, w.o, sc));
+        h.stop2 = h.b2 > 0.0 ? tol * tol * bnorm2[j] / h.b2 : 0.0;
+    }
+    CHK(write_sc(c, SO(c) + k0, HO(c) + k0, cnt));
+    return WCL_OK;
+}
+
+int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const InnerCfg *cfg, SolveWs &w,
+                    const std::vector<double> &bnorm2, std::vector<int> &final_, std::vector<wcl_solve_info> &info)
+{
+    const int n = w.n;
+    const size_t m = d.m;
+    Scalars *sc = SO(c);
+    HIPCHK(launch_copy(P64, n * m, d.bvec, w.r, c->st));
+    HIPCHK(launch_zero(P64, n * m, d.x, c->st));
+    CHK(write_final(c, final_));
+    CHK(restart(c, d, w, -1, o.tol, bnorm2));
+    for (int k = 0; k < n; k++)
+        if (!final_[k] && HO(c)[k].b2 == 0.0) { final_[k] = 1; info[k].status = WCL_OK; }
+    std::vector<int> it_inner(n, 0);
+    std::vector<int> restarts(n, 0);
+    for (int k = 0; k < n; k++) info[k].outer_iters = 0;
+    int iter = 0;
+    const int every = d.flex ? 1 : std::max(1, o.check_every);
+    while (iter < o.max_outer) {
+        bool any_active = false;
+        for (int k = 0; k < n; k++) any_active = any_active || !final_[k];
+        if (!any_active) break;
+        const int chunk = std::min(every, o.max_outer - iter);
+        std::vector<size_t> rec_mark;
+        for (int q = 0; q < chunk; q++) {
+            rec_mark.push_back(c->recs.size());
+            HIPCHK(launch_bicg_p(P64, m, w.r, w.p, w.v, sc, c->st, n, m));
+            void *ph = w.p, *sh = w.s;
+            if (d.flex) {
+                CHK(inner_solve(c, *cfg, w, w.p, w.ph, n, it_inner));
+                for (int k = 0; k < n; k++) info[k].inner_iters_total += final_[k] ? 0 : it_inner[k];
+                ph = w.ph;
+            }
+            CHK(apply_A(c, d, w, ph, w.v, sc));
             {
                 const void *a[1] = {w.rt}, *b[1] = {w.v};
-                HIPCHK(launch_dots(P64, n, 1, a, b, c->partials, sc, c->st));
-                HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st));
+                HIPCHK(launch_dots(P64, m, 1, a, b, c->partials, sc, c->st, n, m));
+                HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n));
             }
-            HIPCHK(launch_bicg_s(P64, n, w.r, w.v, w.s, sc, c->st));
-            CHK(inner_solve(c, cfg, w, w.s, w.sh, &it));
-            inner_total += it;
-            CHK(schur(c, P64, P64, w.sh, w.t, w.o, sc));
+            HIPCHK(launch_bicg_s(P64, m, w.r, w.v, w.s, sc, c->st, n, m));
+            if (d.flex) {
+                CHK(inner_solve(c, *cfg, w, w.s, w.sh, n, it_inner));
+                for (int k = 0; k < n; k++) info[k].inner_iters_total += final_[k] ? 0 : it_inner[k];
+                sh = w.sh;
+            }
+            CHK(apply_A(c, d, w, sh, w.t, sc));
             {
                 const void *a[2] = {w.t, w.t}, *b[2] = {w.s, w.t};
-                HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, sc, c->st));
-                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st));
+                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m));
+                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n));
             }
-            HIPCHK(launch_bicg_xr(P64, n, w.xe, w.ph, w.sh, w.r, w.s, w.t, sc, c->st));
+            HIPCHK(launch_bicg_xr(P64, m, d.x, ph, sh, w.r, w.s, w.t, sc, c->st, n, m));
             {
                 const void *a[2] = {w.rt, w.r}, *b[2] = {w.r, w.r};
-                HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, sc, c->st));
-                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st));
-            }
-            info.outer_iters++;
-            CHK(read_scalars(c, 0));
-            const Scalars &h = c->sc_host[0];
-            if (!std::isfinite(h.r2)) { status = WCL_ENAN; break; }
-            if (h.done == 1 || h.done == 2) {
-                // true residual decides; otherwise replace r and restart
-                HIPCHK(launch_copy(P64, n, w.xe, w.x, c->st));
-                CHK(reconstruct64(c, w.b, w.x, w.o));
-                double rel;
-                CHK(true_residual(c, w, bnorm2, &rel));
-                info.true_relres = rel;
-                if (rel <= o.tol) { status = WCL_OK; break; }
-                CHK(schur(c, P64, P64, w.xe, w.r, w.o, nullptr));
-                HIPCHK(launch_axpby(P64, n, make_double2(1.0, 0.0), w.bh, make_double2(-1.0, 0.0), w.r, c->st));
-                restart_now = true;
-                break;
+                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m));
+                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n));
             }
         }
-        if (!restart_now) break;
+        iter += chunk;
+        CHK(read_sc(c, HO(c), sc, n));
+        bool candidates = false;
+        int exec = 0;  // iterations of this chunk that did work for some right-hand side
+        for (int k = 0; k < n; k++) {
+            if (final_[k]) continue;
+            exec = std::max(exec, HO(c)[k].iter - info[k].outer_iters);
+            info[k].outer_iters = HO(c)[k].iter;
+            if (!std::isfinite(HO(c)[k].r2)) { final_[k] = 1; info[k].status = WCL_ENAN; continue; }
+            if (HO(c)[k].done) candidates = true;
+        }
+        for (size_t q = (size_t)std::max(exec, 0); q < rec_mark.size(); q++) {  // queued after convergence
+            const size_t end = (q + 1 < rec_mark.size()) ? rec_mark[q + 1] : c->recs.size();
+            for (size_t r = rec_mark[q]; r < end; r++) c->recs[r].bytes = c->recs[r].flops = 0.0;
+        }
+        if (!candidates) continue;
+        std::vector<double> rel(n, 0.0);
+        CHK(check_true(c, d, w, bnorm2, rel));
+        bool any_restart = false;
+        for (int k = 0; k < n; k++) {
+            if (final_[k] || !HO(c)[k].done) continue;
+            info[k].true_relres = rel[k];
+            if (rel[k] <= o.tol) { final_[k] = 1; info[k].status = WCL_OK; continue; }
+            if (restarts[k] >= 8) { final_[k] = 1; info[k].status = WCL_ENOCONV; continue; }
+            restarts[k]++;
+            any_restart = true;
+        }
+        CHK(write_final(c, final_));
+        if (any_restart) {
+            // residual replacement: r = b - A x for the restarted right-hand sides
+            CHK(apply_A(c, d, w, d.x, w.t, nullptr));
+            for (int k = 0; k < n; k++) {
+                if (final_[k] || !HO(c)[k].done) continue;
+                const size_t off = (size_t)k * m * 16;
+                HIPCHK(launch_copy(P64, m, (char *)d.bvec + off, (char *)w.r + off, c->st));
+                HIPCHK(launch_axpby(P64, m, make_double2(-1.0, 0.0), (char *)w.t + off, make_double2(1.0, 0.0),
+                                    (char *)w.r + off, c->st));
+                const int it_done = HO(c)[k].iter;
+                CHK(restart(c, d, w, k, o.tol, bnorm2));
+                HO(c)[k].iter = it_done;  // keep counting this right-hand side's iterations
+                CHK(write_sc(c, SO(c) + k, HO(c) + k, 1));
+            }
+        }
     }
-    info.inner_iters_total = inner_total;
-    if (status == WCL_ENOCONV && info.outer_iters >= o.max_outer) status = WCL_ENOCONV;
-    info.status = status;
+    for (int k = 0; k < n; k++)
+        if (!final_[k]) info[k].status = WCL_ENOCONV;
     return WCL_OK;
 }
 
-// Defect correction: x_e += K(r), r = bhat - Dhat x_e in FP64.
-int outer_dc(wcl_ctx *c, const wcl_solve_opts &o, const InnerCfg &cfg, SolveWs &w, double bnorm2,
-             wcl_solve_info &info)
+// Defect correction: x_e += K(r), r = bhat - Dhat x_e in FP64, per right-hand side.
+int outer_dc(wcl_ctx *c, const wcl_solve_opts &o, const InnerCfg &cfg, SolveWs &w, const std::vector<double> &bnorm2,
+             std::vector<int> &final_, std::vector<wcl_solve_info> &info)
 {
-    const size_t n = 12 * (size_t)c->Vh;
-    HIPCHK(launch_copy(P64, n, w.bh, w.r, c->st));
-    HIPCHK(launch_zero(P64, n, w.xe, c->st));
-    int inner_total = 0;
-    info.status = WCL_ENOCONV;
-    while (info.outer_iters < o.max_outer) {
-        int it;
-        CHK(inner_solve(c, cfg, w, w.r, w.ph, &it));
-        inner_total += it;
-        HIPCHK(launch_axpby(P64, n, make_double2(1.0, 0.0), w.ph, make_double2(1.0, 0.0), w.xe, c->st));
-        CHK(schur(c, P64, P64, w.xe, w.r, w.o, nullptr));
-        HIPCHK(launch_axpby(P64, n, make_double2(1.0, 0.0), w.bh, make_double2(-1.0, 0.0), w.r, c->st));
-        info.outer_iters++;
-        double r2;
-        CHK(norm2_host(c, P64, n, w.r, &r2));
-        if (!std::isfinite(r2)) { info.status = WCL_ENAN; break; }
-        if (r2 <= o.tol * o.tol * bnorm2) {
-            HIPCHK(launch_copy(P64, n, w.xe, w.x, c->st));
-            CHK(reconstruct64(c, w.b, w.x, w.o));
-            double rel;
-            CHK(true_residual(c, w, bnorm2, &rel));
-            info.true_relres = rel;
-            if (rel <= o.tol) { info.status = WCL_OK; break; }
+    const int n = w.n;
+    const size_t m = 12 * (size_t)c->Vh;
+    HIPCHK(launch_copy(P64, n * m, w.bh, w.r, c->st));
+    HIPCHK(launch_zero(P64, n * m, w.xe, c->st));
+    std::vector<int> it(n, 0);
+    Driver d{true, m, w.xe, w.bh};
+    for (int outer = 0; outer < o.max_outer; outer++) {
+        bool any_active = false;
+        for (int k = 0; k < n; k++) any_active = any_active || !final_[k];
+        if (!any_active) break;
+        CHK(write_final(c, final_));
+        CHK(inner_solve(c, cfg, w, w.r, w.ph, n, it));
+        for (int k = 0; k < n; k++)
+            if (!final_[k]) { info[k].inner_iters_total += it[k]; info[k].outer_iters++; }
+        // final right-hand sides got K = 0 from the gated inner solve
+        HIPCHK(launch_axpby(P64, n * m, make_double2(1.0, 0.0), w.ph, make_double2(1.0, 0.0), w.xe, c->st));
+        CHK(schur(c, P64, P64, w.xe, w.r, w.o, nullptr, n));
+        HIPCHK(launch_axpby(P64, n * m, make_double2(1.0, 0.0), w.bh, make_double2(-1.0, 0.0), w.r, c->st));
+        std::vector<double> r2(n);
+        CHK(norms_host(c, P64, m, w.r, m, n, r2.data()));
+        bool check = false;
+        for (int k = 0; k < n; k++) {
+            if (final_[k]) continue;
+            if (!std::isfinite(r2[k])) { final_[k] = 1; info[k].status = WCL_ENAN; continue; }
+            if (r2[k] <= o.tol * o.tol * bnorm2[k]) check = true;
+        }
+        if (!check) continue;
+        std::vector<double> rel(n, 0.0);
+        CHK(check_true(c, d, w, bnorm2, rel));
+        for (int k = 0; k < n; k++) {
+            if (final_[k]) continue;
+            info[k].true_relres = rel[k];
+            if (rel[k] <= o.tol) { final_[k] = 1; info[k].status = WCL_OK; }
         }
     }
-    info.inner_iters_total = inner_total;
-    return WCL_OK;
-}
-
-// Plain FP64 BiCGStab on the full D, no preconditioner.
-int plain64(wcl_ctx *c, const wcl_solve_opts &o, SolveWs &w, double bnorm2, wcl_solve_info &info)
-{
-    const size_t n = 24 * (size_t)c->Vh;
-    const size_t e64 = spinor_bytes(8, c->Vh);
-    void *r, *rt, *p, *v, *s, *t;
-    CHK(wsget(c, S_PR, 2 * e64, &r));
-    CHK(wsget(c, S_PRT, 2 * e64, &rt));
-    CHK(wsget(c, S_PP, 2 * e64, &p));
-    CHK(wsget(c, S_PV, 2 * e64, &v));
-    CHK(wsget(c, S_PS, 2 * e64, &s));
-    CHK(wsget(c, S_PT, 2 * e64, &t));
-    Scalars *sc = c->sc;
-    HIPCHK(launch_zero(P64, n, w.x, c->st));
-    HIPCHK(launch_copy(P64, n, w.b, r, c->st));
-    info.status = WCL_ENOCONV;
-    const int every = o.check_every > 0 ? o.check_every : 8;
-    for (int restart = 0; restart < 8; restart++) {
-        HIPCHK(launch_copy(P64, n, r, rt, c->st));
-        HIPCHK(launch_zero(P64, n, p, c->st));
-        HIPCHK(launch_zero(P64, n, v, c->st));
-        {
-            const void *a[2] = {rt, r}, *b[2] = {r, r};
-            HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, nullptr, c->st));
-            HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st));
-        }
-        CHK(read_scalars(c, 0));
-        const double r02 = c->sc_host[0].b2;
-        if (r02 == 0.0) { info.status = WCL_OK; break; }
-        CHK(set_outer_stop(c, o.tol * o.tol * bnorm2 / r02));
-        const int it0 = info.outer_iters;
-        bool stop = false;
-        std::vector<size_t> rec_mark;  // profile records at the start of each queued iteration
-        int queued = 0;
-        while (info.outer_iters < o.max_outer) {
-            const int chunk = std::min(every, o.max_outer - it0 - queued);
-            if (chunk <= 0) break;
-            queued += chunk;
-            for (int k = 0; k < chunk; k++) {
-                rec_mark.push_back(c->recs.size());
-                HIPCHK(launch_bicg_p(P64, n, r, p, v, sc, c->st));
-                CHK(full_D(c, P64, P64, p, v, 0, sc));
-                {
-                    const void *a[1] = {rt}, *b[1] = {v};
-                    HIPCHK(launch_dots(P64, n, 1, a, b, c->partials, sc, c->st));
-                    HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st));
-                }
-                HIPCHK(launch_bicg_s(P64, n, r, v, s, sc, c->st));
-                CHK(full_D(c, P64, P64, s, t, 0, sc));
-                {
-                    const void *a[2] = {t, t}, *b[2] = {s, t};
-                    HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, sc, c->st));
-                    HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st));
-                }
-                HIPCHK(launch_bicg_xr(P64, n, w.x, p, s, r, s, t, sc, c->st));
-                {
-                    const void *a[2] = {rt, r}, *b[2] = {r, r};
-                    HIPCHK(launch_dots(P64, n, 2, a, b, c->partials, sc, c->st));
-                    HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st));
-                }
-            }
-            CHK(read_scalars(c, 0));
-            const Scalars &h = c->sc_host[0];
-            info.outer_iters = it0 + h.iter;
-            for (size_t k = (size_t)h.iter; k < rec_mark.size(); k++) {  // no-op launches
-                const size_t end = (k + 1 < rec_mark.size()) ? rec_mark[k + 1] : c->recs.size();
-                for (size_t q = rec_mark[k]; q < end; q++) c->recs[q].bytes = c->recs[q].flops = 0.0;
-            }
-            if (!std::isfinite(h.r2)) { info.status = WCL_ENAN; stop = true; break; }
-            if (h.done) {
-                double rel;
-                CHK(true_residual(c, w, bnorm2, &rel));
-                info.true_relres = rel;
-                if (rel <= o.tol) { info.status = WCL_OK; stop = true; }
-                else HIPCHK(launch_copy(P64, n, w.res, r, c->st));  // residual replacement
-                break;
-            }
-        }
-        if (stop || info.outer_iters >= o.max_outer) break;
-    }
+    for (int k = 0; k < n; k++)
+        if (!final_[k]) info[k].status = WCL_ENOCONV;
     return WCL_OK;
 }
 
@@ -951,55 +1025,73 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     if (o.outer < 0 || o.outer > WCL_OUTER_PLAIN64) return fail(WCL_EINVAL, "unknown outer solver");
     if (o.inner_prec != 32 && o.inner_prec != 16) return fail(WCL_EINVAL, "inner_prec must be 32 or 16");
     if (o.check_every < 1) o.check_every = 8;
-    if (o.use_ras && o.outer != WCL_OUTER_PLAIN64) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters));
+    const bool plain = o.outer == WCL_OUTER_PLAIN64;
+    if (o.use_ras && !plain) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters));
+    const int n = nrhs;
+    CHK(ensure_batch(c, n));
     SolveWs w;
-    CHK(get_ws(c, w, o.outer != WCL_OUTER_PLAIN64));
+    CHK(get_ws(c, w, !plain, plain, n));
     InnerCfg cfg{o.inner_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every};
     // the inner stopping threshold is fixed for the whole solve
-    {
-        CHK(read_scalars(c, 1));
-        c->sc_host[1].stop2 = o.inner_tol * o.inner_tol;
-        CHK(write_scalars(c, 1));
+    for (int k = 0; k < n; k++) {
+        HI(c)[k] = Scalars{};
+        HI(c)[k].stop2 = o.inner_tol * o.inner_tol;
     }
-    int worst = WCL_OK;
-    for (int k = 0; k < nrhs; k++) {
-        wcl_solve_info info;
-        memset(&info, 0, sizeof(info));
-        HIPCHK(hipStreamSynchronize(c->st));
-        const auto t0 = std::chrono::steady_clock::now();
-        const double *bk = b + (size_t)k * c->V * 24;
-        double *xk = x + (size_t)k * c->V * 24;
-        HIPCHK(launch_pack_spinor(c->g, bk, w.b, c->st));
-        if (o.adjoint) HIPCHK(launch_gamma5(2, c->Vh, w.b, c->st));  // D^dag = g5 D g5
-        double bnorm2;
-        CHK(norm2_host(c, P64, 24 * (size_t)c->Vh, w.b, &bnorm2));
-        if (!std::isfinite(bnorm2)) {
-            info.status = WCL_ENAN;
-        } else if (bnorm2 == 0.0) {
-            HIPCHK(launch_zero(P64, 24 * (size_t)c->Vh, w.x, c->st));
-            info.status = WCL_OK;
-        } else if (o.outer == WCL_OUTER_PLAIN64) {
-            CHK(plain64(c, o, w, bnorm2, info));
+    CHK(write_sc(c, SI(c), HI(c), n));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t fb = full_bytes(P64, c->Vh);
+    for (int k = 0; k < n; k++)
+        HIPCHK(launch_pack_spinor(c->g, b + (size_t)k * c->V * 24, (char *)w.b + k * fb, c->st));
+    if (o.adjoint) HIPCHK(launch_gamma5(2 * (size_t)n, c->Vh, w.b, c->st));  // D^dag = g5 D g5
+    std::vector<double> bnorm2(n);
+    CHK(norms_host(c, P64, 24 * (size_t)c->Vh, w.b, 24 * (size_t)c->Vh, n, bnorm2.data()));
+    std::vector<wcl_solve_info> info(n);
+    std::vector<int> final_(n, 0);
+    for (int k = 0; k < n; k++) {
+        memset(&info[k], 0, sizeof(wcl_solve_info));
+        if (!std::isfinite(bnorm2[k])) { final_[k] = 1; info[k].status = WCL_ENAN; }
+        else if (bnorm2[k] == 0.0) { final_[k] = 1; info[k].status = WCL_OK; }
+    }
+    if (plain) {
+        Driver d{false, 24 * (size_t)c->Vh, w.x, w.b};
+        CHK(bicgstab_driver(c, d, o, nullptr, w, bnorm2, final_, info));
+    } else {
+        CHK(schur_rhs64(c, w.b, w.bh, w.o, w.s, n));
+        if (o.outer == WCL_OUTER_FBICGSTAB) {
+            Driver d{true, 12 * (size_t)c->Vh, w.xe, w.bh};
+            CHK(bicgstab_driver(c, d, o, &cfg, w, bnorm2, final_, info));
         } else {
-            CHK(schur_rhs64(c, w.b, w.bh, w.o, w.s));
-            if (o.outer == WCL_OUTER_FBICGSTAB) CHK(outer_fbicgstab(c, o, cfg, w, bnorm2, info));
-            else CHK(outer_dc(c, o, cfg, w, bnorm2, info));
-            HIPCHK(launch_copy(P64, 12 * (size_t)c->Vh, w.xe, w.x, c->st));
-            CHK(reconstruct64(c, w.b, w.x, w.o));
+            CHK(outer_dc(c, o, cfg, w, bnorm2, final_, info));
         }
-        if (info.status != WCL_ENAN && bnorm2 > 0.0) {
-            double rel;
-            CHK(true_residual(c, w, bnorm2, &rel));
-            info.true_relres = rel;
-            if (info.status == WCL_OK && rel > o.tol) info.status = WCL_ENOCONV;
-            if (!std::isfinite(rel)) info.status = WCL_ENAN;
-        }
-        if (o.adjoint) HIPCHK(launch_gamma5(2, c->Vh, w.x, c->st));
-        HIPCHK(launch_unpack_spinor(c->g, w.x, xk, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (infos) infos[k] = info;
-        if (info.status != WCL_OK && (worst == WCL_OK || info.status == WCL_ENAN)) worst = info.status;
+        HIPCHK(launch_zero(P64, n * 24 * (size_t)c->Vh, w.x, c->st));
+        for (int k = 0; k < n; k++)
+            HIPCHK(hipMemcpyAsync((char *)w.x + k * fb, (char *)w.xe + k * half_bytes(P64, c->Vh),
+                                  half_bytes(P64, c->Vh), hipMemcpyDeviceToDevice, c->st));
+        CHK(reconstruct64(c, w.b, w.x, w.o, n));
+    }
+    // NaN right-hand sides return x = 0
+    for (int k = 0; k < n; k++)
+        if (info[k].status == WCL_ENAN || bnorm2[k] == 0.0)
+            HIPCHK(launch_zero(P64, 24 * (size_t)c->Vh, (char *)w.x + k * fb, c->st));
+    std::vector<double> rel(n, 0.0);
+    CHK(true_residuals(c, w, bnorm2, rel));
+    for (int k = 0; k < n; k++) {
+        if (info[k].status == WCL_ENAN || bnorm2[k] == 0.0) continue;
+        info[k].true_relres = rel[k];
+        if (!std::isfinite(rel[k])) info[k].status = WCL_ENAN;
+        else if (info[k].status == WCL_OK && rel[k] > o.tol) info[k].status = WCL_ENOCONV;
+    }
+    if (o.adjoint) HIPCHK(launch_gamma5(2 * (size_t)n, c->Vh, w.x, c->st));
+    for (int k = 0; k < n; k++)
+        HIPCHK(launch_unpack_spinor(c->g, (char *)w.x + k * fb, x + (size_t)k * c->V * 24, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = WCL_OK;
+    for (int k = 0; k < n; k++) {
+        info[k].seconds = secs;
+        if (infos) infos[k] = info[k];
+        if (info[k].status != WCL_OK && (worst == WCL_OK || info[k].status == WCL_ENAN)) worst = info[k].status;
     }
     if (worst != WCL_OK) {
         const char *what = worst == WCL_ENOCONV ? "solver did not reach the tolerance"

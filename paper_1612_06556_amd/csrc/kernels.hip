@@ -359,7 +359,8 @@ struct HopArgs {
     size_t in_stride, out_stride, x_stride;  // bytes between right-hand sides
     int p;
     int xcd;
-    const Scalars *sc;
+    int nrhs;
+    const Scalars *sc;   // per right-hand side
 };
 
 // The 8 hops of a site run as a two-stage pipeline: the neighbour spinor and
@@ -449,13 +450,18 @@ template <typename SL, typename SS, int MODE, bool DAG, int DEPTH>
 __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 {
     using R = typename Real<SL>::T;
-    if (a.sc && a.sc->done) return;
-    const int bid = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    // workgroup id = site block * nrhs + rhs: the nrhs workgroups of one site
+    // block are neighbours in dispatch order (and on one XCD), so each link
+    // is fetched from HBM once and served to the other right-hand sides by L2
+    const int lin = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int rhs = lin % a.nrhs;
+    const int bid = lin / a.nrhs;
+    if (a.sc && a.sc[rhs].done) return;
     const int h = bid * blockDim.x + threadIdx.x;
     if (h >= a.g.Vh) return;
     const size_t Vh = a.g.Vh;
-    const char *in = (const char *)a.in + blockIdx.y * a.in_stride;
-    char *out = (char *)a.out + blockIdx.y * a.out_stride;
+    const char *in = (const char *)a.in + rhs * a.in_stride;
+    char *out = (char *)a.out + rhs * a.out_stride;
     const Site s = decompose(a.g, h, a.p);
     constexpr int SG = DAG ? -1 : 1;
     cplx<R> acc[12];
@@ -475,14 +481,14 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
             clover_mul(c, acc, o);
         } else if constexpr (MODE == XPAY) {
             cplx<R> xv[12], t[12];
-            load_spinor<SS, R>((const char *)a.x + blockIdx.y * a.x_stride, h, Vh, xv);
+            load_spinor<SS, R>((const char *)a.x + rhs * a.x_stride, h, Vh, xv);
             clover_mul(c, acc, t);
             const R cf = (R)a.coef;
 #pragma unroll
             for (int i = 0; i < 12; i++) o[i] = {fmar(cf, t[i].re, xv[i].re), fmar(cf, t[i].im, xv[i].im)};
         } else {
             cplx<R> xv[12];
-            load_spinor<SS, R>((const char *)a.x + blockIdx.y * a.x_stride, h, Vh, xv);
+            load_spinor<SS, R>((const char *)a.x + rhs * a.x_stride, h, Vh, xv);
             clover_mul(c, xv, o);
             const R cf = (R)a.coef;
 #pragma unroll
@@ -530,9 +536,10 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
     a.p = L.p;
     a.xcd = L.xcd;
     a.sc = L.sc;
+    a.nrhs = L.nrhs > 0 ? L.nrhs : 1;
     const int bs = L.block > 0 ? L.block : 256;
     if (bs > 256 || bs % 64) return hipErrorInvalidValue;
-    dim3 grid((a.g.Vh + bs - 1) / bs, L.nrhs > 0 ? L.nrhs : 1);
+    dim3 grid(((a.g.Vh + bs - 1) / bs) * a.nrhs);
     dim3 block(bs);
     if (L.link_prec == P64 && L.spin_prec == P64) hop_dispatch_mode<double, double>(L, a, grid, block, st);
     else if (L.link_prec == P32 && L.spin_prec == P32) hop_dispatch_mode<float, float>(L, a, grid, block, st);
@@ -545,11 +552,14 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
 // ---------------------------------------------------------------------------
 // Clover apply: out = A in on one parity (504 flop per site).
 template <typename SL, typename SS>
-__global__ void __launch_bounds__(256) k_clover(Geom g, int p, const void *clov, const void *in, void *out)
+__global__ void __launch_bounds__(256) k_clover(Geom g, int p, const void *clov, const char *in, char *out,
+                                               size_t in_stride, size_t out_stride)
 {
     using R = typename Real<SL>::T;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= g.Vh) return;
+    in += blockIdx.y * in_stride;
+    out += blockIdx.y * out_stride;
     R c[72];
     cplx<R> v[12], o[12];
     load_clover<SL, R>(clov, p, h, g.Vh, c);
@@ -559,13 +569,15 @@ __global__ void __launch_bounds__(256) k_clover(Geom g, int p, const void *clov,
 }
 
 hipError_t launch_clover(const Geom &g, int lp, int sp, int p, const void *clov, const void *in, void *out,
-                         hipStream_t st)
+                         hipStream_t st, int nrhs, size_t in_stride, size_t out_stride)
 {
-    dim3 grid((g.Vh + 255) / 256), block(256);
-    if (lp == P64 && sp == P64) k_clover<double, double><<<grid, block, 0, st>>>(g, p, clov, in, out);
-    else if (lp == P32 && sp == P32) k_clover<float, float><<<grid, block, 0, st>>>(g, p, clov, in, out);
-    else if (lp == P16 && sp == P32) k_clover<__half, float><<<grid, block, 0, st>>>(g, p, clov, in, out);
-    else if (lp == P16 && sp == P16) k_clover<__half, __half><<<grid, block, 0, st>>>(g, p, clov, in, out);
+    dim3 grid((g.Vh + 255) / 256, nrhs), block(256);
+    const char *i = (const char *)in;
+    char *o = (char *)out;
+    if (lp == P64 && sp == P64) k_clover<double, double><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P32 && sp == P32) k_clover<float, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P16 && sp == P32) k_clover<__half, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P16 && sp == P16) k_clover<__half, __half><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -574,14 +586,17 @@ hipError_t launch_clover(const Geom &g, int lp, int sp, int p, const void *clov,
 // Precision conversion of spinor sections (each section Vh sites).
 template <typename SI, typename SO>
 __global__ void k_convert(size_t nsites, size_t Vi, size_t Vo, const char *in, char *out, const double *sdev,
-                          int mode, double shost)
+                          int mode, double shost, int sec_per_scale, int sdev_stride)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsites) return;
-    double sc = shost;
-    if (mode == 1) sc = (*sdev > 0.0) ? shost / sqrt(*sdev) : 0.0;
-    else if (mode == 2) sc = shost * sqrt(*sdev);
     const size_t sec = i / Vi, h = i - sec * Vi;
+    double sc = shost;
+    if (mode) {
+        const double v = sdev[(sec / sec_per_scale) * sdev_stride];
+        if (mode == 1) sc = (v > 0.0) ? shost / sqrt(v) : 0.0;
+        else sc = shost * sqrt(v);
+    }
     cplx<double> v[12];
     load_spinor<SI, double>(in + sec * spinor_bytes(sizeof(SI), Vi), h, Vi, v);
 #pragma unroll
@@ -590,12 +605,14 @@ __global__ void k_convert(size_t nsites, size_t Vi, size_t Vo, const char *in, c
 }
 
 hipError_t launch_convert(int ip, int op, size_t nsites, size_t Vi, size_t Vo, const void *in, void *out,
-                          const double *sdev, int mode, double shost, hipStream_t st)
+                          const double *sdev, int mode, double shost, hipStream_t st, int sec_per_scale,
+                          int sdev_stride)
 {
     dim3 grid((unsigned)((nsites + 255) / 256)), block(256);
     const char *i = (const char *)in;
     char *o = (char *)out;
-#define WCL_CONV(A, B) k_convert<A, B><<<grid, block, 0, st>>>(nsites, Vi, Vo, i, o, sdev, mode, shost)
+#define WCL_CONV(A, B) \
+    k_convert<A, B><<<grid, block, 0, st>>>(nsites, Vi, Vo, i, o, sdev, mode, shost, sec_per_scale, sdev_stride)
     if (ip == P64 && op == P32) WCL_CONV(double, float);
     else if (ip == P32 && op == P64) WCL_CONV(float, double);
     else if (ip == P64 && op == P16) WCL_CONV(double, __half);
@@ -643,19 +660,22 @@ struct CT;
 template <> struct CT<double> { using V = double2; };
 template <> struct CT<float> { using V = float2; };
 
-// partials[(2*k + {0,1}) * RED_BLOCKS + block] = (Re, Im) of sum conj(a_k) b_k
+// partials[rhs][(2*k + {0,1}) * RED_BLOCKS + block] = (Re, Im) of sum conj(a_k) b_k
+// over the rhs-th slice (stride elements apart); blockIdx.y = rhs.
 template <typename T, int NP>
-__global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, const typename CT<T>::V *a0, const typename CT<T>::V *b0,
-                                                      const typename CT<T>::V *a1, const typename CT<T>::V *b1,
-                                                      const typename CT<T>::V *a2, const typename CT<T>::V *b2,
-                                                      double *partials, const Scalars *sc)
+__global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, size_t stride, const typename CT<T>::V *a0,
+                                                      const typename CT<T>::V *b0, const typename CT<T>::V *a1,
+                                                      const typename CT<T>::V *b1, const typename CT<T>::V *a2,
+                                                      const typename CT<T>::V *b2, double *partials, const Scalars *sc)
 {
-    if (sc && sc->done) return;
+    const int rhs = blockIdx.y;
+    if (sc && sc[rhs].done) return;
     __shared__ double lds[2 * NP * 16];
     double v[2 * NP];
 #pragma unroll
     for (int k = 0; k < 2 * NP; k++) v[k] = 0.0;
-    const typename CT<T>::V *A[3] = {a0, a1, a2}, *B[3] = {b0, b1, b2};
+    const size_t off = rhs * stride;
+    const typename CT<T>::V *A[3] = {a0 + off, a1 + off, a2 + off}, *B[3] = {b0 + off, b1 + off, b2 + off};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NP; k++) {
@@ -666,19 +686,20 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, const typename C
     }
     block_sum<2 * NP>(v, lds);
     if (threadIdx.x == 0) {
+        double *pr = partials + (size_t)rhs * 6 * RED_BLOCKS;
 #pragma unroll
-        for (int k = 0; k < 2 * NP; k++) partials[k * RED_BLOCKS + blockIdx.x] = v[k];
+        for (int k = 0; k < 2 * NP; k++) pr[k * RED_BLOCKS + blockIdx.x] = v[k];
     }
 }
 
 hipError_t launch_dots(int prec, size_t n, int np, const void *const *a, const void *const *b, double *partials,
-                       const Scalars *sc, hipStream_t st)
+                       const Scalars *sc, hipStream_t st, int nrhs, size_t stride)
 {
     const void *A[3] = {a[0], np > 1 ? a[1] : a[0], np > 2 ? a[2] : a[0]};
     const void *B[3] = {b[0], np > 1 ? b[1] : b[0], np > 2 ? b[2] : b[0]};
-    dim3 grid(RED_BLOCKS), block(RED_THREADS);
+    dim3 grid(RED_BLOCKS, nrhs), block(RED_THREADS);
 #define WCL_DOTS(T, NP)                                                                                   \
-    k_dots<T, NP><<<grid, block, 0, st>>>(n, (const CT<T>::V *)A[0], (const CT<T>::V *)B[0],              \
+    k_dots<T, NP><<<grid, block, 0, st>>>(n, stride, (const CT<T>::V *)A[0], (const CT<T>::V *)B[0],      \
                                           (const CT<T>::V *)A[1], (const CT<T>::V *)B[1],                 \
                                           (const CT<T>::V *)A[2], (const CT<T>::V *)B[2], partials, sc)
     if (prec == P64) {
@@ -703,8 +724,14 @@ WCL_D void cdiv(const double a[2], const double b[2], double o[2])
     o[1] = (a[1] * b[0] - a[0] * b[1]) / d;
 }
 
-__global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const double *partials, Scalars *sc)
+// One workgroup per right-hand side.  gate (optional): a right-hand side
+// whose gate scalars are done is marked done at BICG_INIT_RHO.
+__global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const double *partials_all, Scalars *sc_all,
+                                                  const Scalars *gate)
 {
+    const int rhs = blockIdx.x;
+    Scalars *sc = sc_all + rhs;
+    const double *partials = partials_all + (size_t)rhs * 6 * RED_BLOCKS;
     if (sc->done && (step == BICG_ALPHA || step == BICG_OMEGA || step == BICG_RHO)) return;
     __shared__ double lds[6 * 16];
     double v[6];
@@ -728,6 +755,7 @@ __global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const do
         sc->omega[0] = 1.0; sc->omega[1] = 0.0;
         sc->iter = 0;
         sc->done = (v[2] == 0.0) ? 1 : 0;
+        if (gate && gate[rhs].done) sc->done = 1;
         break;
     case BICG_ALPHA: {
         const double d[2] = {v[0], v[1]};
@@ -759,22 +787,23 @@ __global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const do
     }
 }
 
-hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st)
+hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st, int nrhs,
+                           const Scalars *gate)
 {
-    k_finalize<<<1, 256, 0, st>>>(step, nterms, partials, sc);
+    k_finalize<<<nrhs, 256, 0, st>>>(step, nterms, partials, sc, gate);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab vector updates (complex scalars from the device).
+// BiCGStab vector updates (complex scalars from the device), blockIdx.y = rhs.
 template <typename T>
-WCL_D typename CT<T>::V cv(double re, double im) { return {(T)re, (T)im}; }
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_bicg_p(size_t n, const typename CT<T>::V *r, typename CT<T>::V *p,
-                                               const typename CT<T>::V *v, const Scalars *sc)
+__global__ void __launch_bounds__(256) k_bicg_p(size_t n, size_t stride, const typename CT<T>::V *r,
+                                               typename CT<T>::V *p, const typename CT<T>::V *v, const Scalars *sc_all)
 {
+    const Scalars *sc = sc_all + blockIdx.y;
     if (sc->done) return;
+    const size_t off = blockIdx.y * stride;
+    r += off; p += off; v += off;
     // beta = (rho / rho_old) (alpha / omega)
     double q1[2], q2[2], beta[2];
     cdiv(sc->rho, sc->rho_old, q1);
@@ -792,10 +821,13 @@ __global__ void __launch_bounds__(256) k_bicg_p(size_t n, const typename CT<T>::
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_bicg_s(size_t n, const typename CT<T>::V *r, const typename CT<T>::V *v,
-                                               typename CT<T>::V *s, const Scalars *sc)
+__global__ void __launch_bounds__(256) k_bicg_s(size_t n, size_t stride, const typename CT<T>::V *r,
+                                               const typename CT<T>::V *v, typename CT<T>::V *s, const Scalars *sc_all)
 {
+    const Scalars *sc = sc_all + blockIdx.y;
     if (sc->done) return;
+    const size_t off = blockIdx.y * stride;
+    r += off; v += off; s += off;
     const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const auto rv = r[i], vv = v[i];
@@ -804,12 +836,15 @@ __global__ void __launch_bounds__(256) k_bicg_s(size_t n, const typename CT<T>::
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_bicg_xr(size_t n, typename CT<T>::V *x, const typename CT<T>::V *ph,
-                                                const typename CT<T>::V *sh, typename CT<T>::V *r,
-                                                const typename CT<T>::V *s, const typename CT<T>::V *t,
-                                                const Scalars *sc)
+__global__ void __launch_bounds__(256) k_bicg_xr(size_t n, size_t stride, typename CT<T>::V *x,
+                                                const typename CT<T>::V *ph, const typename CT<T>::V *sh,
+                                                typename CT<T>::V *r, const typename CT<T>::V *s,
+                                                const typename CT<T>::V *t, const Scalars *sc_all)
 {
+    const Scalars *sc = sc_all + blockIdx.y;
     if (sc->done) return;
+    const size_t off = blockIdx.y * stride;
+    x += off; ph += off; sh += off; r += off; s += off; t += off;
     const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1], wr = (T)sc->omega[0], wi = (T)sc->omega[1];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const auto xv = x[i], pv = ph[i], sv = sh[i], s2 = s[i], tv = t[i];
@@ -819,43 +854,50 @@ __global__ void __launch_bounds__(256) k_bicg_xr(size_t n, typename CT<T>::V *x,
     }
 }
 
-static dim3 blas_grid(size_t n)
+static dim3 blas_grid(size_t n, int nrhs = 1)
 {
     size_t b = (n + 255) / 256;
-    if (b > 8192) b = 8192;
+    const size_t cap = nrhs > 1 ? 2048 : 8192;
+    if (b > cap) b = cap;
     if (b < 1) b = 1;
-    return dim3((unsigned)b);
+    return dim3((unsigned)b, nrhs);
 }
 
 hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
-                         hipStream_t st)
+                         hipStream_t st, int nrhs, size_t stride)
 {
     if (prec == P64)
-        k_bicg_p<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)r, (double2 *)p, (const double2 *)v, sc);
+        k_bicg_p<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const double2 *)r, (double2 *)p,
+                                                            (const double2 *)v, sc);
     else
-        k_bicg_p<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)r, (float2 *)p, (const float2 *)v, sc);
+        k_bicg_p<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const float2 *)r, (float2 *)p,
+                                                           (const float2 *)v, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void *s, const Scalars *sc,
-                         hipStream_t st)
+                         hipStream_t st, int nrhs, size_t stride)
 {
     if (prec == P64)
-        k_bicg_s<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)r, (const double2 *)v, (double2 *)s, sc);
+        k_bicg_s<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const double2 *)r, (const double2 *)v,
+                                                            (double2 *)s, sc);
     else
-        k_bicg_s<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)r, (const float2 *)v, (float2 *)s, sc);
+        k_bicg_s<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const float2 *)r, (const float2 *)v,
+                                                           (float2 *)s, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r, const void *s,
-                          const void *t, const Scalars *sc, hipStream_t st)
+                          const void *t, const Scalars *sc, hipStream_t st, int nrhs, size_t stride)
 {
     if (prec == P64)
-        k_bicg_xr<double><<<blas_grid(n), 256, 0, st>>>(n, (double2 *)x, (const double2 *)ph, (const double2 *)sh,
-                                                        (double2 *)r, (const double2 *)s, (const double2 *)t, sc);
+        k_bicg_xr<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (double2 *)x, (const double2 *)ph,
+                                                             (const double2 *)sh, (double2 *)r, (const double2 *)s,
+                                                             (const double2 *)t, sc);
     else
-        k_bicg_xr<float><<<blas_grid(n), 256, 0, st>>>(n, (float2 *)x, (const float2 *)ph, (const float2 *)sh,
-                                                       (float2 *)r, (const float2 *)s, (const float2 *)t, sc);
+        k_bicg_xr<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (float2 *)x, (const float2 *)ph,
+                                                            (const float2 *)sh, (float2 *)r, (const float2 *)s,
+                                                            (const float2 *)t, sc);
     return hipGetLastError();
 }
 

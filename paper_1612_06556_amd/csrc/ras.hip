@@ -28,6 +28,8 @@ struct RasArgs {
     const void *clov_inv;
     float kappa2;
     const Scalars *sc;
+    int nrhs;
+    size_t stride;   // bytes between right-hand sides
 };
 
 // global (tile coordinate, in-tile coordinate) of extended-block coordinate a
@@ -175,7 +177,14 @@ WCL_D void block_allreduce(double v[NV], double *red)
 template <typename SL, int MAXNE>
 __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 {
-    if (a.sc && a.sc->done) return;
+    // workgroup id = tile * nrhs + rhs (the right-hand sides of one tile share
+    // its links and clover through L2)
+    const int lin = xcd_block(blockIdx.x, gridDim.x);
+    const int rhs = lin % a.nrhs;
+    const int blk = lin / a.nrhs;
+    if (a.sc && a.sc[rhs].done) return;
+    const float4 *rin = (const float4 *)((const char *)a.in + rhs * a.stride);
+    float4 *rout = (float4 *)((char *)a.out + rhs * a.stride);
     // component-major with the compile-time stride MAXNE (immediate LDS offsets)
     __shared__ float2 sE[12 * MAXNE];   // MR residual r on the even block sites
     __shared__ float2 sO[12 * MAXNE];   // y = A_oo^-1 H_oe r on the odd block sites
@@ -187,7 +196,6 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     const int e0 = g.B[0] + 2 * d, e1 = g.B[1] + 2 * d, e2 = g.B[2] + 2 * d, e3 = g.B[3] + 2 * d;
     const int Ne = (e0 * e1 * e2 * e3) >> 1;
     const int e0h = e0 >> 1;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
     int bc[4];
     {
         int r = blk;
@@ -269,7 +277,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     // r = the input on the even block sites (zero start: z = 0, r = rhs)
     if (active) {
         cplx<float> r[12];
-        load_spinor<float, float>(a.in, gE, Vh, r);
+        load_spinor<float, float>(rin, gE, Vh, r);
 #pragma unroll
         for (int c = 0; c < 12; c++) sE[c * MAXNE + t] = make_float2(r[c].re, r[c].im);
     }
@@ -317,7 +325,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 #pragma unroll
                     for (int c = 0; c < 12; c++) z[c] = {0.f, 0.f};
                 } else {
-                    load_spinor<float, float>(a.out, gE, Vh, z);
+                    load_spinor<float, float>(rout, gE, Vh, z);
                 }
             }
 #pragma unroll
@@ -326,7 +334,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
                 if (core) z[c] = {z[c].re + ar * r.x - ai * r.y, z[c].im + ar * r.y + ai * r.x};
                 sE[c * MAXNE + t] = make_float2(r.x - (ar * qv[c].re - ai * qv[c].im), r.y - (ar * qv[c].im + ai * qv[c].re));
             }
-            if (core) store_spinor<float, float>(a.out, gE, Vh, z);
+            if (core) store_spinor<float, float>(rout, gE, Vh, z);
         }
     }
 }
@@ -357,10 +365,12 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.clov_inv = L.clov_inv;
     a.kappa2 = L.kappa2;
     a.sc = L.sc;
+    a.nrhs = L.nrhs > 0 ? L.nrhs : 1;
+    a.stride = L.stride;
     const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     const int threads = ras_threads(g, L.overlap);
     if (threads > 1024) return hipErrorInvalidValue;
-    dim3 grid(nblk), block(threads);
+    dim3 grid(nblk * a.nrhs), block(threads);
     if (ne <= 128) {
         if (L.link_prec == P32) k_ras<float, 128><<<grid, block, 0, st>>>(a);
         else if (L.link_prec == P16) k_ras<__half, 128><<<grid, block, 0, st>>>(a);
@@ -383,7 +393,8 @@ void ras_work(const RasLaunch &L, double *bytes, double *flops)
 {
     const Geom &g = *L.g;
     const double lb = L.link_prec == P32 ? 72.0 : 36.0, cb = L.link_prec == P32 ? 288.0 : 144.0;
-    *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + 2.0 * 96.0);
+    const double nr = L.nrhs > 0 ? L.nrhs : 1;
+    *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + nr * 2.0 * 96.0);
     int e[4];
     double ext = 1.0;
     for (int mu = 0; mu < 4; mu++) {
@@ -397,7 +408,7 @@ void ras_work(const RasLaunch &L, double *bytes, double *flops)
     // two dot products (96) and the z, r updates (96)
     const double per_iter = hops * 168.0 + ext * 504.0 + ne * (48.0 + 96.0 + 96.0);
     const double nblk = (double)g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
-    *flops = per_iter * L.iters * nblk;
+    *flops = per_iter * L.iters * nblk * nr;
 }
 
 }  // namespace wcl

@@ -54,7 +54,8 @@ void ras_work(const struct RasLaunch &a, double *bytes, double *flops);
 
 // out = A in on parity p (A = clover field).
 hipError_t launch_clover(const Geom &g, int link_prec, int spin_prec, int p, const void *clov,
-                         const void *in, void *out, hipStream_t st);
+                         const void *in, void *out, hipStream_t st, int nrhs = 1, size_t in_stride = 0,
+                         size_t out_stride = 0);
 
 // Canonical complex128 [V][4][3] <-> e/o FP64 field [2][12][Vh] double2.
 hipError_t launch_pack_spinor(const Geom &g, const double *canon, void *eo, hipStream_t st);
@@ -69,12 +70,13 @@ hipError_t launch_clover_build(const Geom &g, const void *u64, double csw_kappa,
                                void *t32, void *ti32, void *t16, void *ti16, int *info_dev,
                                hipStream_t st);
 
-// Spinor precision conversion of n sites (both layouts hold 12 complex per
-// site): out = scale * in, with scale read from scale_dev (if non-null, as
-// 1 / sqrt(*scale_dev) when inv_sqrt) times scale_host.
+// Spinor precision conversion of nsites sites in sections of Vh sites (both
+// layouts hold 12 complex per site): out = scale * in.  mode 0: scale =
+// scale_host; mode 1: scale_host / sqrt(v); mode 2: scale_host * sqrt(v), with
+// v = scale_dev[(section / sec_per_scale) * sdev_stride].
 hipError_t launch_convert(int in_prec, int out_prec, size_t nsites, size_t Vh_in, size_t Vh_out,
-                          const void *in, void *out, const double *scale_dev, int inv_sqrt,
-                          double scale_host, hipStream_t st);
+                          const void *in, void *out, const double *scale_dev, int mode,
+                          double scale_host, hipStream_t st, int sec_per_scale = 1, int sdev_stride = 0);
 
 // ---------------------------------------------------------------------------
 // Reductions and BLAS-1 on flat complex arrays (length n complex numbers).
@@ -94,9 +96,11 @@ struct Scalars {
     int pad[2];
 };
 
-// dot partials: for each (a_k, b_k) pair listed, sum conj(a_k) b_k.
+// dot partials: for each (a_k, b_k) pair listed, sum conj(a_k) b_k, per
+// right-hand side (slices `stride` complex numbers apart); partials hold
+// [nrhs][6][RED_BLOCKS] doubles.
 hipError_t launch_dots(int prec, size_t n, int npairs, const void *const *a, const void *const *b,
-                       double *partials, const Scalars *sc, hipStream_t st);
+                       double *partials, const Scalars *sc, hipStream_t st, int nrhs = 1, size_t stride = 0);
 
 // BiCGStab building blocks (complex scalars taken from Scalars).
 enum BicgStep {
@@ -106,17 +110,19 @@ enum BicgStep {
     BICG_RHO = 3,        // rho_old = rho; rho = <rt, r>; r2 = |r|^2; done if r2 <= stop2 b2
     NORM_ONLY = 4,       // t[0] = |v|^2
 };
-hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st);
+hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st,
+                           int nrhs = 1, const Scalars *gate = nullptr);
 
 // p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
 hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
-                         hipStream_t st);
+                         hipStream_t st, int nrhs = 1, size_t stride = 0);
 // s = r - alpha v
 hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void *s, const Scalars *sc,
-                         hipStream_t st);
+                         hipStream_t st, int nrhs = 1, size_t stride = 0);
 // x += alpha ph + omega sh ; r = s - omega t
 hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r,
-                          const void *s, const void *t, const Scalars *sc, hipStream_t st);
+                          const void *s, const void *t, const Scalars *sc, hipStream_t st, int nrhs = 1,
+                          size_t stride = 0);
 
 // Generic complex axpby: y = a x + b y, a and b host constants.
 hipError_t launch_axpby(int prec, size_t n, double2 a, const void *x, double2 b, void *y, hipStream_t st);
@@ -134,7 +140,9 @@ struct RasLaunch {
     const void *links;
     const void *clov_inv;
     float kappa2;
-    const Scalars *sc;   // may be null; skips when sc->done
+    const Scalars *sc;   // may be null; per right-hand side, skips when done
+    int nrhs;            // right-hand sides, fields `stride` bytes apart
+    size_t stride;
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 

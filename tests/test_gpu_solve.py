@@ -128,3 +128,37 @@ def test_invalid_arguments():
     assert e.value.code == wcl.WCL_ESTATE
     with pytest.raises(wcl.WclError):
         lat.set_ras(3, 4)  # 4 + 2*3 > 8
+
+
+@pytest.mark.parametrize("inner_prec", [32, 16])
+def test_batched_point_sources_8x4(inner_prec):
+    """The 12 spin-colour point sources at the origin solved together (one set
+    of launches for all right-hand sides): each x_k against its own oracle
+    solve and residual."""
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = synth.point_sources(dims)
+    x, infos, rc = lat.solve(to_gpu(b), tol=1e-10, inner_prec=inner_prec)
+    x = to_host(x)
+    assert rc == 0 and len(infos) == 12
+    for k in range(12):
+        assert infos[k]["status"] == 0
+        assert _oracle_residual(orc, x[k], b[k]) <= 1e-10
+        xr, _ = orc.bicgstab_eo(b[k], 1e-13, 20000)
+        assert rel(x[k], xr) <= 1e-8, k
+    print("batched", infos[0], flush=True)
+
+
+def test_batched_mixed_outer_variants():
+    """Batched defect correction and batched plain FP64 on 3 Gaussian sources."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = synth.gaussian_spinor(dims, 41, nrhs=3)
+    for kw in (dict(outer=wcl.OUTER_DC, inner_tol=1e-3), dict(outer=wcl.OUTER_PLAIN64, max_outer=5000),
+               dict(use_ras=0)):
+        x, infos, rc = lat.solve(to_gpu(b), tol=1e-10, **kw)
+        x = to_host(x)
+        assert rc == 0, kw
+        for k in range(3):
+            assert _oracle_residual(orc, x[k], b[k]) <= 1e-10, (kw, k)
