@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the ablation solves")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of known size "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -76,6 +79,13 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     V = int(np.prod(DIMS))
     Vh = V // 2
     U = synth.su3_field(DIMS, 1003)
@@ -133,7 +143,9 @@ def main():
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = round(d["ms"] * 1e3 / max(d["launches"], 1), 2)
     roof["share_of_gpu_time"] = round(d["ms"] / sum(s["ms"] for s in stats.values()), 3)
-    kernel_classes = {k: {"launches": s["launches"], "gpu_ms_per_step": round(s["ms"] / args.steps, 3),
+    kernel_classes = {k: {"launches": s["launches"], "idle_launches": s["idle_launches"],
+                          "idle_ms_per_step": round(s["idle_ms"] / args.steps, 3),
+                          "gpu_ms_per_step": round(s["ms"] / args.steps, 3),
                           "GB/s": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1),
                           "TFLOP/s": round(s["flops"] / max(s["ms"], 1e-9) / 1e9, 3)} for k, s in stats.items()}
 
@@ -164,11 +176,26 @@ def main():
                                           "GB/s": round(byts * Vh / ms / 1e6, 1),
                                           "frac_hbm": round(byts * Vh / ms / 1e6 / HBM_PEAK_GBS, 4)}
         out["hop_standalone"] = hop
+        # measured streaming ceiling: device-to-device copy of 2 x 1 GiB
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * src.numel() * 4 / (time.perf_counter() - t1) / 1e9
+        out["copy_ceiling_GBps"] = round(copy_gbs, 1)
+        out["hop_fp32_cold_frac_of_copy"] = round(hop["fp32_cold"]["GB/s"] / copy_gbs, 3)
+        del src, dst
         out["hop_fp32_cold_vs_paper_knc_200gflops"] = round(hop["fp32_cold"]["GFlop/s"] / PAPER_KNC_HOP_GFLOPS, 1)
         # time-to-solution variants (one warm run each)
         sol = {}
         for name, kw in (("mixed_ras_fp32", opts),
+                         ("mixed_ras_fp32_graph", dict(opts, use_graph=1)),
                          ("mixed_noras_fp32", dict(opts, use_ras=0)),
+                         ("mixed_noras_fp32_graph", dict(opts, use_ras=0, use_graph=1)),
                          ("mixed_ras_fp16", dict(opts, inner_prec=16)),
                          ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
                          ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):

@@ -150,22 +150,24 @@ int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_c
  * synchronises the stream and returns the totals of one class. */
 enum { WCL_K_HOP = 0, WCL_K_RAS = 1, WCL_K_CLOVER = 2, WCL_K_COUNT = 3 };
 typedef struct {
-    int launches;
-    int pad;
-    double ms;       /* summed event time of the launches */
-    double bytes;    /* summed algorithmic HBM bytes       */
-    double flops;    /* summed flops (conventions above)   */
+    int launches;        /* launches that did work                            */
+    int idle_launches;   /* launches queued after convergence (no-ops)        */
+    double ms;           /* summed event time of the working launches         */
+    double bytes;        /* summed algorithmic HBM bytes                      */
+    double flops;        /* summed flops (conventions above)                  */
+    double idle_ms;      /* summed event time of the no-op launches           */
 } wcl_kstat;
 int wcl_profile(wcl_ctx *ctx, int enable);
 int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
 
 /* Launch configuration of the hopping kernel: threads per workgroup (64, 128,
- * 256), pipeline depth (2, 3, 4: hops of a site whose neighbour spinor and
- * link are in flight while an earlier hop is computed) and XCD-aware
- * workgroup order (0/1).  wcl_autotune_hop times every combination with
+ * 256), pipeline depth (2, 3: hops of a site whose neighbour spinor and
+ * link are in flight while an earlier hop is computed), XCD-aware workgroup
+ * order (0/1) and non-temporal link/clover loads (0/1; single right-hand
+ * side only).  wcl_autotune_hop times every block/depth/xcd combination with
  * wcl_bench_hop (prec, `copies` field sets) and keeps the fastest; best[3]
  * (may be NULL) receives {block, depth, xcd}. */
-int wcl_set_tuning(wcl_ctx *ctx, int hop_block, int hop_depth, int hop_xcd);
+int wcl_set_tuning(wcl_ctx *ctx, int hop_block, int hop_depth, int hop_xcd, int hop_nontemporal);
 int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
 
 const char *wcl_last_error(void);

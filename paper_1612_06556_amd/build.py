@@ -22,12 +22,30 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the library."""
+    import concurrent.futures
+    import tempfile
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    out_tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", out_tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory() as tmp:
+        jobs = []
+        for src in sources():
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
+            flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+            jobs.append(([hipcc, *flags, *inc, "-c", src, "-o", obj], obj))
+        if verbose:
+            for cmd, _ in jobs:
+                print(" ".join(cmd), flush=True)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+            for res in ex.map(lambda j: subprocess.run(j[0], capture_output=True, text=True), jobs):
+                if res.returncode != 0:
+                    raise RuntimeError("hipcc failed:\n" + res.stderr)
+        out_tmp = LIB + ".tmp"
+        link = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", out_tmp, *[o for _, o in jobs]]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(out_tmp, LIB)
     return LIB
 

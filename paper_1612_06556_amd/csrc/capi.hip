@@ -67,7 +67,7 @@ struct wcl_ctx {
     Scalars *sc_host = nullptr; // pinned mirror
     int cap = 0;                // right-hand sides the scalar and partial buffers hold
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
-    int hop_block = 256, hop_depth = 2, hop_xcd = 1;
+    int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0;
     // event profiling of kernel classes
     struct Rec {
         int kclass;
@@ -133,6 +133,7 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     L.xcd = c->hop_xcd;
     L.block = c->hop_block;
     L.depth = c->hop_depth;
+    L.nontemporal = c->hop_nt;
     return L;
 }
 
@@ -656,6 +657,9 @@ struct InnerCfg {
     int maxit;
     bool ras;
     int check_every;
+    bool graph;                    // replay the iteration as a captured hipGraph
+    hipGraphExec_t *exec;          // the captured iteration (created on first use)
+    hipStream_t cap_stream;        // private stream used only for the capture
 };
 
 // One BiCGStab iteration (right preconditioned by RAS when enabled) on the
@@ -743,9 +747,28 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
     Scalars *h = HI(c);
     while (launched < cfg.maxit) {
         chunk = std::max(1, std::min(chunk, cfg.maxit - launched));
+        if (cfg.graph && !*cfg.exec) {
+            // capture one iteration (kernel launches only, no memset or copy
+            // nodes); the buffers and scalars it touches are fixed for the solve
+            const bool prof = c->prof;
+            hipStream_t st = c->st;
+            c->prof = false;
+            c->st = cfg.cap_stream;
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(cfg.cap_stream, hipStreamCaptureModeThreadLocal));
+            const int rc = inner_iteration(c, cfg, w, sc, n);
+            const hipError_t ec = hipStreamEndCapture(cfg.cap_stream, &graph);
+            c->st = st;
+            c->prof = prof;
+            if (rc != WCL_OK) return rc;
+            HIPCHK(ec);
+            HIPCHK(hipGraphInstantiate(cfg.exec, graph, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(graph);
+        }
         for (int k = 0; k < chunk; k++) {
             rec_mark.push_back(c->recs.size());
-            CHK(inner_iteration(c, cfg, w, sc, n));
+            if (cfg.graph) HIPCHK(hipGraphLaunch(*cfg.exec, c->st));
+            else CHK(inner_iteration(c, cfg, w, sc, n));
         }
         launched += chunk;
         CHK(read_sc(c, h, sc, n));
@@ -1031,7 +1054,20 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     CHK(ensure_batch(c, n));
     SolveWs w;
     CHK(get_ws(c, w, !plain, plain, n));
-    InnerCfg cfg{o.inner_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every};
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    if (o.use_graph && !plain) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    struct GraphGuard {
+        hipGraphExec_t *e;
+        hipStream_t *s;
+        ~GraphGuard()
+        {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*s) (void)hipStreamDestroy(*s);
+        }
+    } guard{&graph_exec, &cap_stream};
+    InnerCfg cfg{o.inner_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every,
+                 o.use_graph != 0 && !plain, &graph_exec, cap_stream};
     // the inner stopping threshold is fixed for the whole solve
     for (int k = 0; k < n; k++) {
         HI(c)[k] = Scalars{};
@@ -1214,10 +1250,15 @@ extern "C" int wcl_profile_read(wcl_ctx *c, int kclass, wcl_kstat *out)
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
         wcl_kstat &k = c->stats[r.kclass];
-        k.launches += 1;
-        k.ms += ms;
-        k.bytes += r.bytes;
-        k.flops += r.flops;
+        if (r.flops > 0.0) {  // launches that did work (not no-ops queued past convergence)
+            k.launches += 1;
+            k.ms += ms;
+            k.bytes += r.bytes;
+            k.flops += r.flops;
+        } else {
+            k.idle_launches += 1;
+            k.idle_ms += ms;
+        }
         c->pool.push_back(r.e0);
         c->pool.push_back(r.e1);
     }
@@ -1226,32 +1267,33 @@ extern "C" int wcl_profile_read(wcl_ctx *c, int kclass, wcl_kstat *out)
     return WCL_OK;
 }
 
-extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_xcd)
+extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_xcd, int hop_nontemporal)
 {
     if (!c) return fail(WCL_EINVAL, "null context");
     if (hop_block != 64 && hop_block != 128 && hop_block != 256) return fail(WCL_EINVAL, "hop_block must be 64, 128 or 256");
-    if (hop_depth < 2 || hop_depth > 4) return fail(WCL_EINVAL, "hop_depth must be 2, 3 or 4");
+    if (hop_depth < 2 || hop_depth > 3) return fail(WCL_EINVAL, "hop_depth must be 2 or 3");
     c->hop_block = hop_block;
     c->hop_depth = hop_depth;
     c->hop_xcd = hop_xcd ? 1 : 0;
+    c->hop_nt = hop_nontemporal ? 1 : 0;
     return WCL_OK;
 }
 
 extern "C" int wcl_autotune_hop(wcl_ctx *c, int prec, int copies, int *best)
 {
     if (!c) return fail(WCL_EINVAL, "null context");
-    const int blocks[3] = {64, 128, 256}, depths[3] = {2, 3, 4};
+    const int blocks[3] = {64, 128, 256}, depths[2] = {2, 3};
     double best_ms = 1e30;
     int bb = c->hop_block, bo = c->hop_depth, bx = c->hop_xcd;
     for (int xcd = 0; xcd < 2; xcd++)
         for (int ib = 0; ib < 3; ib++)
-            for (int io = 0; io < 3; io++) {
-                CHK(wcl_set_tuning(c, blocks[ib], depths[io], xcd));
+            for (int io = 0; io < 2; io++) {
+                CHK(wcl_set_tuning(c, blocks[ib], depths[io], xcd, c->hop_nt));
                 double ms;
                 CHK(wcl_bench_hop(c, prec, 50, copies, &ms));
                 if (ms < best_ms) { best_ms = ms; bb = blocks[ib]; bo = depths[io]; bx = xcd; }
             }
-    CHK(wcl_set_tuning(c, bb, bo, bx));
+    CHK(wcl_set_tuning(c, bb, bo, bx, c->hop_nt));
     if (best) { best[0] = bb; best[1] = bo; best[2] = bx; }
     return WCL_OK;
 }

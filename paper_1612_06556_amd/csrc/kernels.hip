@@ -390,7 +390,7 @@ WCL_D void pipeline_fence(cplx<R> acc[12], uint32_t &hn, uint32_t &h)
                    "+v"(acc[10].re), "+v"(acc[10].im), "+v"(acc[11].re), "+v"(acc[11].im), "+v"(hn), "+v"(h));
 }
 
-template <typename SL, typename SS, int K, typename R>
+template <typename SL, typename SS, int K, bool NT, typename R>
 WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, HopStage<R> &st,
                     cplx<R> acc[12])
 {
@@ -402,8 +402,8 @@ WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in
     uint32_t h = h0;
     pipeline_fence(acc, hn, h);
     load_spinor<SS, R>(in, hn, Vh, st.psi);
-    if (FWD) load_link<SL, R>(a.links, MU, a.p, h, Vh, st.u);
-    else load_link<SL, R>(a.links, MU, 1 - a.p, hn, Vh, st.u);
+    if (FWD) load_link<SL, R, NT>(a.links, MU, a.p, h, Vh, st.u);
+    else load_link<SL, R, NT>(a.links, MU, 1 - a.p, hn, Vh, st.u);
     st.sign = R(1);
     if (MU == 3 && g.tbc < 0 && s.x[3] == (FWD ? g.L[3] - 1 : 0)) st.sign = R(-1);
 }
@@ -424,29 +424,32 @@ WCL_D void hop_compute(const HopStage<R> &st, cplx<R> acc[12])
     accumulate<MU, S, R>(acc, uh);
 }
 
-template <typename SL, typename SS, int SG, int D, int K, typename R>
+template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
 WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
                         cplx<R> acc[12])
 {
     if constexpr (K < D - 1) {
-        hop_load<SL, SS, K, R>(a, s, h, in, st[K], acc);
-        hop_prologue<SL, SS, SG, D, K + 1, R>(a, s, h, in, st, acc);
+        hop_load<SL, SS, K, NT, R>(a, s, h, in, st[K], acc);
+        hop_prologue<SL, SS, SG, D, K + 1, NT, R>(a, s, h, in, st, acc);
     }
 }
 
 // hop K is computed while the operands of hop K + D - 1 are in flight
-template <typename SL, typename SS, int SG, int D, int K, typename R>
+template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
 WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
                         cplx<R> acc[12])
 {
     if constexpr (K < 8) {
-        if constexpr (K + D - 1 < 8) hop_load<SL, SS, K + D - 1, R>(a, s, h, in, st[(K + D - 1) % D], acc);
+        if constexpr (K + D - 1 < 8) hop_load<SL, SS, K + D - 1, NT, R>(a, s, h, in, st[(K + D - 1) % D], acc);
         hop_compute<K, SG, R>(st[K % D], acc);
-        hop_pipeline<SL, SS, SG, D, K + 1, R>(a, s, h, in, st, acc);
+        hop_pipeline<SL, SS, SG, D, K + 1, NT, R>(a, s, h, in, st, acc);
     }
 }
 
-template <typename SL, typename SS, int MODE, bool DAG, int DEPTH>
+// NT: links and clover loaded non-temporally (a single right-hand side reads
+// them once per launch).  Off by default: repeated applications in a solver
+// find the links in the Infinity Cache only when they were loaded normally.
+template <typename SL, typename SS, int MODE, bool DAG, int DEPTH, bool NT>
 __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 {
     using R = typename Real<SL>::T;
@@ -468,14 +471,14 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = {R(0), R(0)};
     HopStage<R> st[DEPTH];
-    hop_prologue<SL, SS, SG, DEPTH, 0, R>(a, s, h, in, st, acc);
-    hop_pipeline<SL, SS, SG, DEPTH, 0, R>(a, s, h, in, st, acc);
+    hop_prologue<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
+    hop_pipeline<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
 
     if constexpr (MODE == HOP) {
         store_spinor<SS, R>(out, h, Vh, acc);
     } else {
         R c[72];
-        load_clover<SL, R>(a.clov, a.p, h, Vh, c);
+        load_clover<SL, R, NT>(a.clov, a.p, h, Vh, c);
         cplx<R> o[12];
         if constexpr (MODE == CLOV_H) {
             clover_mul(c, acc, o);
@@ -498,15 +501,17 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     }
 }
 
-// Pipeline-depth variants (hops whose operands are in flight: 2, 3, 4).
-// D^dag launches use depth 2 only.
+// Pipeline-depth variants (hops whose operands are in flight: 2, 3) times
+// temporal / non-temporal operator loads.  D^dag launches use depth 2.
 template <typename SL, typename SS, int MODE>
 static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
 {
-    if (L.dagger) k_hop<SL, SS, MODE, true, 2><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 4) k_hop<SL, SS, MODE, false, 4><<<grid, block, 0, st>>>(a);
-    else k_hop<SL, SS, MODE, false, 2><<<grid, block, 0, st>>>(a);
+    const bool nt = L.nontemporal && a.nrhs == 1;
+    if (L.dagger) k_hop<SL, SS, MODE, true, 2, false><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 3 && nt) k_hop<SL, SS, MODE, false, 3, true><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3, false><<<grid, block, 0, st>>>(a);
+    else if (nt) k_hop<SL, SS, MODE, false, 2, true><<<grid, block, 0, st>>>(a);
+    else k_hop<SL, SS, MODE, false, 2, false><<<grid, block, 0, st>>>(a);
 }
 
 template <typename SL, typename SS>

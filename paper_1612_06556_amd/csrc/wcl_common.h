@@ -240,6 +240,35 @@ WCL_D T ldf(const void *base, uint32_t off)
 {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
+// Non-temporal variant for data read exactly once per launch (links, clover
+// of the hopping kernel): keeps it from evicting reusable lines from L2.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+WCL_D T ldf_nt(const void *base, uint32_t off)
+{
+    const char *p = reinterpret_cast<const char *>(base) + off;
+    T r;
+    if constexpr (sizeof(T) == 16) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        __builtin_memcpy(&r, &v, 16);
+    } else if constexpr (sizeof(T) == 8) {
+        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        __builtin_memcpy(&r, &v, 8);
+    } else {
+        const unsigned int v = __builtin_nontemporal_load(reinterpret_cast<const unsigned int *>(p));
+        __builtin_memcpy(&r, &v, 4);
+    }
+    return r;
+}
+
+template <bool NT, typename T>
+WCL_D T ldx(const void *base, uint32_t off)
+{
+    if constexpr (NT) return ldf_nt<T>(base, off);
+    else return ldf<T>(base, off);
+}
+
 template <typename T>
 WCL_D void stf(void *base, uint32_t off, const T &v)
 {
@@ -300,36 +329,36 @@ WCL_D void store_spinor(void *base, uint32_t h, uint32_t Vh, const cplx<R> v[12]
 }
 
 // Link U_mu at (parity p, half index h): 9 complex, row-major.
-template <typename S, typename R>
+template <typename S, typename R, bool NT = false>
 WCL_D void load_link(const void *base, int mu, int p, uint32_t h, uint32_t Vh, cplx<R> u[9])
 {
     const uint32_t mp = (uint32_t)(mu * 2 + p);
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t i = 0; i < 9; i++) {
-            const double2 d = ldf<double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
+            const double2 d = ldx<NT, double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
             u[i] = {(R)d.x, (R)d.y};
         }
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
         for (uint32_t k = 0; k < 4; k++) {
-            const float4 f = ldf<float4>(base, ((mp * 4 + k) * Vh + h) * 16u);
+            const float4 f = ldx<NT, float4>(base, ((mp * 4 + k) * Vh + h) * 16u);
             u[2 * k] = {(R)f.x, (R)f.y};
             u[2 * k + 1] = {(R)f.z, (R)f.w};
         }
-        const float2 f = ldf<float2>(base, 32u * Vh * 16u + (mp * Vh + h) * 8u);
+        const float2 f = ldx<NT, float2>(base, 32u * Vh * 16u + (mp * Vh + h) * 8u);
         u[8] = {(R)f.x, (R)f.y};
     } else {
 #pragma unroll
         for (uint32_t k = 0; k < 2; k++) {
-            const uint4 w = ldf<uint4>(base, ((mp * 2 + k) * Vh + h) * 16u);
+            const uint4 w = ldx<NT, uint4>(base, ((mp * 2 + k) * Vh + h) * 16u);
             float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w);
             u[4 * k + 0] = {(R)a.x, (R)a.y};
             u[4 * k + 1] = {(R)b.x, (R)b.y};
             u[4 * k + 2] = {(R)c.x, (R)c.y};
             u[4 * k + 3] = {(R)d.x, (R)d.y};
         }
-        const float2 f = h2f2(ldf<uint32_t>(base, 16u * Vh * 16u + (mp * Vh + h) * 4u));
+        const float2 f = h2f2(ldx<NT, uint32_t>(base, 16u * Vh * 16u + (mp * Vh + h) * 4u));
         u[8] = {(R)f.x, (R)f.y};
     }
 }
@@ -371,26 +400,26 @@ WCL_HD size_t spinor_bytes(int S_size, size_t Vh) { return (S_size == 8 ? 192 : 
 WCL_HD size_t clover_bytes(int S_size, size_t Vh) { return 2 * (S_size == 8 ? 576 : S_size == 4 ? 288 : 144) * Vh; }
 
 // Clover site (72 reals) at (parity p, h).
-template <typename S, typename R>
+template <typename S, typename R, bool NT = false>
 WCL_D void load_clover(const void *base, int p, uint32_t h, uint32_t Vh, R c[72])
 {
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t k = 0; k < 36; k++) {
-            const double2 d = ldf<double2>(base, (((uint32_t)p * 36 + k) * Vh + h) * 16u);
+            const double2 d = ldx<NT, double2>(base, (((uint32_t)p * 36 + k) * Vh + h) * 16u);
             c[2 * k] = (R)d.x;
             c[2 * k + 1] = (R)d.y;
         }
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
         for (uint32_t k = 0; k < 18; k++) {
-            const float4 f = ldf<float4>(base, (((uint32_t)p * 18 + k) * Vh + h) * 16u);
+            const float4 f = ldx<NT, float4>(base, (((uint32_t)p * 18 + k) * Vh + h) * 16u);
             c[4 * k] = f.x; c[4 * k + 1] = f.y; c[4 * k + 2] = f.z; c[4 * k + 3] = f.w;
         }
     } else {
 #pragma unroll
         for (uint32_t k = 0; k < 9; k++) {
-            const uint4 w = ldf<uint4>(base, (((uint32_t)p * 9 + k) * Vh + h) * 16u);
+            const uint4 w = ldx<NT, uint4>(base, (((uint32_t)p * 9 + k) * Vh + h) * 16u);
             float2 a = h2f2(w.x), b = h2f2(w.y), cc = h2f2(w.z), d = h2f2(w.w);
             c[8 * k + 0] = a.x; c[8 * k + 1] = a.y; c[8 * k + 2] = b.x; c[8 * k + 3] = b.y;
             c[8 * k + 4] = cc.x; c[8 * k + 5] = cc.y; c[8 * k + 6] = d.x; c[8 * k + 7] = d.y;

@@ -37,7 +37,8 @@ struct HopLaunch {
     size_t in_stride, out_stride, x_stride;
     int xcd;            // XCD-aware workgroup order
     int block;          // threads per workgroup (64..256)
-    int depth;          // hops whose operands are in flight per thread (2, 3, 4)
+    int depth;          // hops whose operands are in flight per thread (2, 3)
+    int nontemporal;    // links / clover loaded non-temporally (single right-hand side only)
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
 };
 

@@ -47,8 +47,8 @@ class wcl_solve_info(ctypes.Structure):
 
 
 class wcl_kstat(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int), ("pad", ctypes.c_int), ("ms", ctypes.c_double),
-                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int), ("idle_launches", ctypes.c_int), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double), ("idle_ms", ctypes.c_double)]
 
 
 K_HOP, K_RAS, K_CLOVER = 0, 1, 2
@@ -83,7 +83,7 @@ def load():
     lib.wcl_destroy.argtypes = [_vp]
     lib.wcl_profile.argtypes = [_vp, ctypes.c_int]
     lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
-    lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     _lib = lib
     return lib
@@ -169,11 +169,12 @@ def wcl_profile(h, enable):
 def wcl_profile_read(h, kclass):
     k = wcl_kstat()
     _check(load().wcl_profile_read(h, int(kclass), ctypes.byref(k)))
-    return {"launches": k.launches, "ms": k.ms, "bytes": k.bytes, "flops": k.flops}
+    return {"launches": k.launches, "ms": k.ms, "bytes": k.bytes, "flops": k.flops,
+            "idle_launches": k.idle_launches, "idle_ms": k.idle_ms}
 
 
-def wcl_set_tuning(h, hop_block, hop_depth, hop_xcd):
-    _check(load().wcl_set_tuning(h, int(hop_block), int(hop_depth), int(hop_xcd)))
+def wcl_set_tuning(h, hop_block, hop_depth, hop_xcd, hop_nontemporal=0):
+    _check(load().wcl_set_tuning(h, int(hop_block), int(hop_depth), int(hop_xcd), int(hop_nontemporal)))
 
 
 def wcl_autotune_hop(h, prec, copies):

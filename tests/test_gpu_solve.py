@@ -162,3 +162,18 @@ def test_batched_mixed_outer_variants():
         assert rc == 0, kw
         for k in range(3):
             assert _oracle_residual(orc, x[k], b[k]) <= 1e-10, (kw, k)
+
+
+def test_graph_replay_matches_eager():
+    """The inner iteration replayed as a captured hipGraph gives bitwise the
+    same solution as the eagerly launched one (same kernels, same order),
+    on every replay of a multi-iteration solve, twice in a row."""
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = to_gpu(synth.gaussian_spinor(dims, 2001, nrhs=2))
+    x0, i0, rc0 = lat.solve(b, use_graph=0)
+    for _ in range(2):
+        x1, i1, rc1 = lat.solve(b, use_graph=1)
+        assert rc0 == 0 and rc1 == 0
+        assert np.array_equal(to_host(x0), to_host(x1))
+        assert [i["inner_iters_total"] for i in i0] == [i["inner_iters_total"] for i in i1]
