@@ -563,7 +563,7 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             HIPCHK(launch_zero(P64, 12 * Vh, par(b64, P64, Vh, 1), c->st));
             break;
         case WCL_OP_RAS: {
-            RasLaunch R;
+            RasLaunch R{};
             R.g = &c->g;
             R.overlap = c->ras_overlap;
             R.iters = c->ras_iters;
@@ -574,6 +574,8 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.clov_inv = clovinv_for(c, lp);
             R.kappa2 = (float)(c->kappa * c->kappa);
             R.sc = nullptr;
+            R.nrhs = 1;
+            R.stride = 0;
             CHK(run_ras(c, R));
             HIPCHK(launch_zero(P64, 12 * Vh, par(b64, P64, Vh, 1), c->st));
             break;
@@ -670,7 +672,7 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
     const int lp = cfg.lprec;
     HIPCHK(launch_bicg_p(P32, m, w.r32, w.p32, w.v32, sc, c->st, n, m));
     void *ph = w.p32, *sh = w.s32;
-    RasLaunch R;
+    RasLaunch R{};
     if (cfg.ras) {
         R.g = &c->g;
         R.overlap = c->ras_overlap;

@@ -527,6 +527,11 @@ static void hop_dispatch_mode(const HopLaunch &L, const HopArgs &a, dim3 grid, d
 
 hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
 {
+    if (L.nrhs < 1 || L.nrhs > 4096) return hipErrorInvalidValue;
+    if (L.nrhs > 1) {
+        const size_t sb = spinor_bytes(L.spin_prec == P64 ? 8 : L.spin_prec == P32 ? 4 : 2, (size_t)L.g->Vh);
+        if (L.in_stride < sb || L.out_stride < sb || (L.mode >= XPAY && L.x_stride < sb)) return hipErrorInvalidValue;
+    }
     HopArgs a;
     a.g = *L.g;
     a.in = L.in;
@@ -541,7 +546,7 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
     a.p = L.p;
     a.xcd = L.xcd;
     a.sc = L.sc;
-    a.nrhs = L.nrhs > 0 ? L.nrhs : 1;
+    a.nrhs = L.nrhs;
     const int bs = L.block > 0 ? L.block : 256;
     if (bs > 256 || bs % 64) return hipErrorInvalidValue;
     dim3 grid(((a.g.Vh + bs - 1) / bs) * a.nrhs);

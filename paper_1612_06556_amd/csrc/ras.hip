@@ -350,6 +350,9 @@ int ras_threads(const Geom &g, int overlap)
 hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
 {
     const Geom &g = *L.g;
+    // several right-hand sides need a stride of at least one even field
+    if (L.nrhs < 1 || L.nrhs > 4096) return hipErrorInvalidValue;
+    if (L.nrhs > 1 && L.stride < spinor_bytes(4, (size_t)g.Vh)) return hipErrorInvalidValue;
     for (int mu = 0; mu < 4; mu++)
         if (L.overlap > g.B[mu] || g.L[mu] < g.B[mu] + 2 * L.overlap) return hipErrorInvalidValue;
     int ne = 1;
@@ -365,7 +368,7 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.clov_inv = L.clov_inv;
     a.kappa2 = L.kappa2;
     a.sc = L.sc;
-    a.nrhs = L.nrhs > 0 ? L.nrhs : 1;
+    a.nrhs = L.nrhs;
     a.stride = L.stride;
     const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     const int threads = ras_threads(g, L.overlap);

@@ -118,3 +118,22 @@ def test_bench_shape_24x32():
         e = rel(to_host(lat.apply(g, prec=prec)), ref)
         print(f"D 24^3x32 prec={prec} rel={e:.3e}", flush=True)
         assert e <= TOL[prec]
+
+
+def test_ras_op_launch_accounting():
+    """One RAS application through wcl_apply_op is one launch over the tiles
+    of one right-hand side: its recorded work equals the single-rhs count."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    psi = synth.gaussian_spinor(dims, 3)
+    lat.set_ras(1, 4)
+    wcl.wcl_profile(lat.h, 1)
+    lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=32)
+    st = wcl.wcl_profile_read(lat.h, wcl.K_RAS)
+    wcl.wcl_profile(lat.h, 0)
+    # per block and MR step: in-block hops x 168 + 1296 x 504 + 648 x 240; 16 tiles, 4 steps
+    hops = 2 * 4 * 5 * 6 ** 3
+    expect = (hops * 168 + 1296 * 504 + 648 * 240) * 4 * 16
+    assert st["launches"] == 1
+    assert st["flops"] == expect
