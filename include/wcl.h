@@ -75,6 +75,18 @@ int wcl_set_gauge(wcl_ctx *ctx, const double *U_dev);
  * clover block is not positive definite. */
 int wcl_set_params(wcl_ctx *ctx, double kappa, double csw);
 
+/* Two-row (12-real) link storage for the FP32 and FP16 tiers (enable 1) or
+ * full 3x3 links (0, the default).  An SU(3) matrix is fixed by its first two
+ * rows (row 2 = conj(row0 x row1)), so the hopping and Schwarz kernels read
+ * 48 (FP32) or 24 (FP16) bytes per link instead of 72 / 36 and rebuild the
+ * third row in registers; FP64 work always uses the full links.  Enabling
+ * checks, on the current and every later wcl_set_gauge, that each link is
+ * SU(3) to 1e-7 (row norms, row orthogonality, row 2 against the cross
+ * product); otherwise the call fails with WCL_EINVAL and, in wcl_set_gauge,
+ * the context has no gauge field until the next successful call.  With
+ * compression on, wcl_set_gauge synchronises the stream for that check. */
+int wcl_set_compression(wcl_ctx *ctx, int enable);
+
 /* out = D in (dagger = 0) or D^dag in (dagger = 1) on nrhs full-lattice
  * spinors, computed with links, clover and vectors stored in prec
  * (64, 32: FP32 storage and arithmetic, 16: FP16 storage, FP32 arithmetic).

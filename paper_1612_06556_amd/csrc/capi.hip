@@ -56,6 +56,8 @@ struct wcl_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
+    void *U32c = nullptr, *U16c = nullptr;  // two-row links (built when compression is on)
+    int compress = 0;                       // FP32/FP16 tiers read the two-row links
     void *T64 = nullptr, *Ti64 = nullptr, *T32 = nullptr, *Ti32 = nullptr, *T16 = nullptr, *Ti16 = nullptr;
     int *info = nullptr;
     double kappa = 0, csw = 0;
@@ -111,9 +113,31 @@ int wsget(wcl_ctx *c, int slot, size_t bytes, void **out)
     return WCL_OK;
 }
 
-void *links_for(wcl_ctx *c, int prec) { return prec == P64 ? c->U64 : prec == P32 ? c->U32 : c->U16; }
-void *clov_for(wcl_ctx *c, int prec) { return prec == P64 ? c->T64 : prec == P32 ? c->T32 : c->T16; }
-void *clovinv_for(wcl_ctx *c, int prec) { return prec == P64 ? c->Ti64 : prec == P32 ? c->Ti32 : c->Ti16; }
+// Link storage the kernels read for a precision tier (two-row links when on).
+int eff_lprec(const wcl_ctx *c, int prec)
+{
+    if (c->compress && prec == P32) return P32C;
+    if (c->compress && prec == P16) return P16C;
+    return prec;
+}
+void *links_for(wcl_ctx *c, int prec)
+{
+    switch (prec) {
+        case P64: return c->U64;
+        case P32: return c->U32;
+        case P16: return c->U16;
+        case P32C: return c->U32c;
+        default: return c->U16c;
+    }
+}
+void *clov_for(wcl_ctx *c, int prec)
+{
+    return prec == P64 ? c->T64 : (prec == P32 || prec == P32C) ? c->T32 : c->T16;
+}
+void *clovinv_for(wcl_ctx *c, int prec)
+{
+    return prec == P64 ? c->Ti64 : (prec == P32 || prec == P32C) ? c->Ti32 : c->Ti16;
+}
 
 char *par(void *field, int prec, size_t Vh, int p) { return (char *)field + p * spinor_bytes(prec_bytes(prec), Vh); }
 const char *par(const void *field, int prec, size_t Vh, int p)
@@ -126,9 +150,9 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     HopLaunch L;
     memset(&L, 0, sizeof(L));
     L.g = &c->g;
-    L.link_prec = lprec;
+    L.link_prec = eff_lprec(c, lprec);
     L.spin_prec = sprec;
-    L.links = links_for(c, lprec);
+    L.links = links_for(c, L.link_prec);
     L.nrhs = 1;
     L.xcd = c->hop_xcd;
     L.block = c->hop_block;
@@ -360,9 +384,43 @@ enum Slot {
     S_PR, S_PRT, S_PP, S_PV, S_PS, S_PT, S_PX,
     // gradient
     S_GX, S_GY, S_GK, S_GG, S_GHX, S_GCX,
+    // SU(3) check partials
+    S_SU3,
     // bench copies start here
     S_BENCH = 64,
 };
+
+// Largest SU(3) defect accepted for two-row link storage (the FP32 tier's
+// own rounding is 6e-8).
+constexpr double SU3_TOL = 1e-7;
+
+// Check that the FP64 links are SU(3) (two-row storage rebuilds row 2 as
+// conj(row0 x row1)), then write the FP32 and FP16 two-row copies.
+int build_compressed(wcl_ctx *c)
+{
+    const size_t Vh = c->Vh;
+    if (!c->U32c) {
+        CHK(alloc(&c->U32c, link_bytes_c(P32C, Vh)));
+        CHK(alloc(&c->U16c, link_bytes_c(P16C, Vh)));
+    }
+    const int nb = 256;
+    void *part;
+    CHK(wsget(c, S_SU3, nb * sizeof(double), &part));
+    HIPCHK(launch_su3_check(c->g, c->U64, (double *)part, nb, c->st));
+    std::vector<double> h(nb);
+    HIPCHK(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double m = 0.0;
+    for (double d : h)
+        if (d > m || d != d) m = d;
+    if (!(m <= SU3_TOL)) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "two-row link storage needs SU(3) links: largest defect %.3e > %.1e", m, SU3_TOL);
+        return fail(WCL_EINVAL, msg);
+    }
+    HIPCHK(launch_compress_links(c->g, c->U64, c->U32c, c->U16c, c->st));
+    return WCL_OK;
+}
 
 }  // namespace
 
@@ -437,7 +495,7 @@ int wcl_destroy(wcl_ctx *c)
 {
     if (!c) return WCL_OK;
     (void)hipStreamSynchronize(c->st);
-    void *ptrs[] = {c->U64, c->U32, c->U16, c->T64, c->Ti64, c->T32, c->Ti32, c->T16, c->Ti16, c->info,
+    void *ptrs[] = {c->U64, c->U32, c->U16, c->U32c, c->U16c, c->T64, c->Ti64, c->T32, c->Ti32, c->T16, c->Ti16, c->info,
                     c->partials, c->sc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -453,6 +511,7 @@ int wcl_destroy(wcl_ctx *c)
     return WCL_OK;
 }
 
+
 int wcl_set_gauge(wcl_ctx *c, const double *U)
 {
     if (!c || !U) return fail(WCL_EINVAL, "null argument");
@@ -463,8 +522,26 @@ int wcl_set_gauge(wcl_ctx *c, const double *U)
         CHK(alloc(&c->U16, link_bytes(2, Vh)));
     }
     HIPCHK(launch_ingest_gauge(c->g, U, c->U64, c->U32, c->U16, c->st));
-    c->have_gauge = true;
+    c->have_gauge = false;
     c->have_params = false;
+    if (c->compress) CHK(build_compressed(c));
+    c->have_gauge = true;
+    return WCL_OK;
+}
+
+extern "C" int wcl_set_compression(wcl_ctx *c, int enable)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    if (enable != 0 && enable != 1) return fail(WCL_EINVAL, "enable must be 0 or 1");
+    if (enable && c->have_gauge && !c->compress) {
+        c->compress = 1;
+        const int rc = build_compressed(c);
+        if (rc != WCL_OK) {
+            c->compress = 0;
+            return rc;
+        }
+    }
+    c->compress = enable;
     return WCL_OK;
 }
 
@@ -567,10 +644,10 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.g = &c->g;
             R.overlap = c->ras_overlap;
             R.iters = c->ras_iters;
-            R.link_prec = lp;
+            R.link_prec = eff_lprec(c, lp);
             R.in = par(a, sp, Vh, 0);
             R.out = par(b, sp, Vh, 0);
-            R.links = links_for(c, lp);
+            R.links = links_for(c, R.link_prec);
             R.clov_inv = clovinv_for(c, lp);
             R.kappa2 = (float)(c->kappa * c->kappa);
             R.sc = nullptr;
@@ -677,8 +754,8 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         R.g = &c->g;
         R.overlap = c->ras_overlap;
         R.iters = c->ras_iters;
-        R.link_prec = lp;
-        R.links = links_for(c, lp);
+        R.link_prec = eff_lprec(c, lp);
+        R.links = links_for(c, R.link_prec);
         R.clov_inv = clovinv_for(c, lp);
         R.kappa2 = (float)(c->kappa * c->kappa);
         R.sc = sc;
@@ -1148,8 +1225,8 @@ extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double 
     if (prec != 32 && prec != 16) return fail(WCL_EINVAL, "bench prec must be 32 or 16");
     if (reps < 1 || copies < 1 || copies > 32) return fail(WCL_EINVAL, "reps >= 1 and 1 <= copies <= 32 required");
     const size_t Vh = c->Vh;
-    const int lb = prec_bytes(prec);
-    const size_t lbytes = link_bytes(lb, Vh), sbytes = spinor_bytes(4, Vh);
+    const int lb = prec_bytes(prec), ep = eff_lprec(c, prec);
+    const size_t lbytes = ep == prec ? link_bytes(lb, Vh) : link_bytes_c(ep, Vh), sbytes = spinor_bytes(4, Vh);
     std::vector<void *> lk(copies), in(copies), out(copies);
     for (int k = 0; k < copies; k++) {
         if (k == 0) lk[k] = links_for(c, prec);

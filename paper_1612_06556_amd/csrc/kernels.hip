@@ -104,6 +104,70 @@ __global__ void k_ingest_gauge(Geom g, const double2 *__restrict__ canon, void *
     }
 }
 
+// Two-row (12-real) FP32 and FP16 copies of the FP64 links.
+__global__ void k_compress_links(Geom g, const void *u64, void *u32c, void *u16c)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * g.Vh) return;
+    const int mp = i / g.Vh, h = i - mp * g.Vh;
+    cplx<double> u[9];
+    load_link<double, double>(u64, mp >> 1, mp & 1, h, g.Vh, u);
+    store_link<R12f, double>(u32c, mp >> 1, mp & 1, h, g.Vh, u);
+    store_link<R12h, double>(u16c, mp >> 1, mp & 1, h, g.Vh, u);
+}
+
+hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, hipStream_t st)
+{
+    k_compress_links<<<(8 * g.Vh + 255) / 256, 256, 0, st>>>(g, u64, u32c, u16c);
+    return hipGetLastError();
+}
+
+// Largest |row2 - conj(row0 x row1)| over the FP64 links (per-workgroup maxima).
+// max that keeps a NaN (fmax would drop it)
+WCL_D double nanmax(double m, double d) { return (d > m || d != d) ? d : m; }
+
+__global__ void __launch_bounds__(256) k_su3_check(Geom g, const void *u64, double *partial)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 8 * g.Vh; i += gridDim.x * blockDim.x) {
+        const int mp = i / g.Vh, h = i - mp * g.Vh;
+        cplx<double> u[9], r[9];
+        load_link<double, double>(u64, mp >> 1, mp & 1, h, g.Vh, u);
+#pragma unroll
+        for (int k = 0; k < 9; k++) r[k] = u[k];
+        su3_third_row(r);
+#pragma unroll
+        for (int k = 6; k < 9; k++) m = nanmax(m, fmax(fabs(r[k].re - u[k].re), fabs(r[k].im - u[k].im)));
+        cplx<double> ip = {0.0, 0.0};
+        double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const cplx<double> a = u[c], b = u[3 + c];
+            n0 += a.re * a.re + a.im * a.im;
+            n1 += b.re * b.re + b.im * b.im;
+            ip.re += a.re * b.re + a.im * b.im;
+            ip.im += a.re * b.im - a.im * b.re;
+        }
+        m = nanmax(m, fabs(n0 - 1.0));
+        m = nanmax(m, fabs(n1 - 1.0));
+        m = nanmax(m, sqrt(ip.re * ip.re + ip.im * ip.im));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_su3_check(const Geom &g, const void *u64, double *partial, int nblocks, hipStream_t st)
+{
+    k_su3_check<<<nblocks, 256, 0, st>>>(g, u64, partial);
+    return hipGetLastError();
+}
+
 hipError_t launch_ingest_gauge(const Geom &g, const double *canon, void *u64, void *u32, void *u16,
                                hipStream_t st)
 {
@@ -478,7 +542,7 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
         store_spinor<SS, R>(out, h, Vh, acc);
     } else {
         R c[72];
-        load_clover<SL, R, NT>(a.clov, a.p, h, Vh, c);
+        load_clover<typename ClovS<SL>::T, R, NT>(a.clov, a.p, h, Vh, c);
         cplx<R> o[12];
         if constexpr (MODE == CLOV_H) {
             clover_mul(c, acc, o);
@@ -555,6 +619,9 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
     else if (L.link_prec == P32 && L.spin_prec == P32) hop_dispatch_mode<float, float>(L, a, grid, block, st);
     else if (L.link_prec == P16 && L.spin_prec == P32) hop_dispatch_mode<__half, float>(L, a, grid, block, st);
     else if (L.link_prec == P16 && L.spin_prec == P16) hop_dispatch_mode<__half, __half>(L, a, grid, block, st);
+    else if (L.link_prec == P32C && L.spin_prec == P32) hop_dispatch_mode<R12f, float>(L, a, grid, block, st);
+    else if (L.link_prec == P16C && L.spin_prec == P32) hop_dispatch_mode<R12h, float>(L, a, grid, block, st);
+    else if (L.link_prec == P16C && L.spin_prec == P16) hop_dispatch_mode<R12h, __half>(L, a, grid, block, st);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -584,6 +651,8 @@ hipError_t launch_clover(const Geom &g, int lp, int sp, int p, const void *clov,
     dim3 grid((g.Vh + 255) / 256, nrhs), block(256);
     const char *i = (const char *)in;
     char *o = (char *)out;
+    if (lp == P32C) lp = P32;
+    if (lp == P16C) lp = P16;
     if (lp == P64 && sp == P64) k_clover<double, double><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
     else if (lp == P32 && sp == P32) k_clover<float, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
     else if (lp == P16 && sp == P32) k_clover<__half, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
@@ -962,9 +1031,15 @@ hipError_t launch_zero(int prec, size_t n, void *y, hipStream_t st)
 
 namespace wcl {
 
-static double link_site_bytes(int prec) { return prec == P64 ? 144.0 : prec == P32 ? 72.0 : 36.0; }
+static double link_site_bytes(int prec)
+{
+    return prec == P64 ? 144.0 : prec == P32 ? 72.0 : prec == P16 ? 36.0 : prec == P32C ? 48.0 : 24.0;
+}
 static double spinor_site_bytes(int prec) { return prec == P64 ? 192.0 : prec == P32 ? 96.0 : 48.0; }
-static double clover_site_bytes(int prec) { return prec == P64 ? 576.0 : prec == P32 ? 288.0 : 144.0; }
+static double clover_site_bytes(int prec)
+{
+    return prec == P64 ? 576.0 : (prec == P32 || prec == P32C) ? 288.0 : 144.0;
+}
 
 void hop_work(const HopLaunch &a, double *bytes, double *flops)
 {

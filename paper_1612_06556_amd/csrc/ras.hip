@@ -144,7 +144,7 @@ WCL_D void ras_clover(const void *clov, int q, uint32_t gq, uint32_t Vh, cplx<fl
         uint32_t gc = gq, dummy = 0;
         ras_fence(acc, gc, dummy);
         float cl[36];
-        load_clover_half<SL, float>(clov, q, gc, Vh, half, cl);
+        load_clover_half<typename ClovS<SL>::T, float>(clov, q, gc, Vh, half, cl);
         clover_mul_half(cl, acc + 6 * half, out + 6 * half);
     }
 }
@@ -377,10 +377,14 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     if (ne <= 128) {
         if (L.link_prec == P32) k_ras<float, 128><<<grid, block, 0, st>>>(a);
         else if (L.link_prec == P16) k_ras<__half, 128><<<grid, block, 0, st>>>(a);
+        else if (L.link_prec == P32C) k_ras<R12f, 128><<<grid, block, 0, st>>>(a);
+        else if (L.link_prec == P16C) k_ras<R12h, 128><<<grid, block, 0, st>>>(a);
         else return hipErrorInvalidValue;
     } else if (ne <= 648) {
         if (L.link_prec == P32) k_ras<float, 648><<<grid, block, 0, st>>>(a);
         else if (L.link_prec == P16) k_ras<__half, 648><<<grid, block, 0, st>>>(a);
+        else if (L.link_prec == P32C) k_ras<R12f, 648><<<grid, block, 0, st>>>(a);
+        else if (L.link_prec == P16C) k_ras<R12h, 648><<<grid, block, 0, st>>>(a);
         else return hipErrorInvalidValue;
     } else {
         return hipErrorInvalidValue;
@@ -395,7 +399,8 @@ namespace wcl {
 void ras_work(const RasLaunch &L, double *bytes, double *flops)
 {
     const Geom &g = *L.g;
-    const double lb = L.link_prec == P32 ? 72.0 : 36.0, cb = L.link_prec == P32 ? 288.0 : 144.0;
+    const double lb = L.link_prec == P32 ? 72.0 : L.link_prec == P16 ? 36.0 : L.link_prec == P32C ? 48.0 : 24.0;
+    const double cb = (L.link_prec == P32 || L.link_prec == P32C) ? 288.0 : 144.0;
     const double nr = L.nrhs > 0 ? L.nrhs : 1;
     *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + nr * 2.0 * 96.0);
     int e[4];

@@ -29,6 +29,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define WCL_HD __host__ __device__ __forceinline__
 #define WCL_D __device__ __forceinline__
 
@@ -218,9 +220,17 @@ WCL_D void accumulate(cplx<R> acc[12], const cplx<R> uh[6])
 }
 
 // ---------------------------------------------------------------------------
-// Storage formats.
+// Storage formats.  R12f / R12h: links stored as their first two rows (12
+// reals, FP32 / FP16); the third row of an SU(3) matrix is conj(row0 x row1)
+// and is rebuilt in registers.  The clover field of those tiers is FP32 /
+// FP16.
+struct R12f {};
+struct R12h {};
 template <typename S> struct Real { using T = float; };
 template <> struct Real<double> { using T = double; };
+template <typename S> struct ClovS { using T = S; };
+template <> struct ClovS<R12f> { using T = float; };
+template <> struct ClovS<R12h> { using T = __half; };
 
 WCL_D float2 h2f2(uint32_t u)
 {
@@ -278,6 +288,7 @@ WCL_D void stf(void *base, uint32_t off, const T &v)
 template <typename S, typename R>
 WCL_D void load_spinor(const void *base, uint32_t h, uint32_t Vh, cplx<R> v[12])
 {
+    static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t i = 0; i < 12; i++) {
@@ -307,6 +318,7 @@ WCL_D void load_spinor(const void *base, uint32_t h, uint32_t Vh, cplx<R> v[12])
 template <typename S, typename R>
 WCL_D void store_spinor(void *base, uint32_t h, uint32_t Vh, const cplx<R> v[12])
 {
+    static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t i = 0; i < 12; i++) stf(base, (i * Vh + h) * 16u, make_double2((double)v[i].re, (double)v[i].im));
@@ -329,11 +341,40 @@ WCL_D void store_spinor(void *base, uint32_t h, uint32_t Vh, const cplx<R> v[12]
 }
 
 // Link U_mu at (parity p, half index h): 9 complex, row-major.
+template <typename R>
+WCL_D void su3_third_row(cplx<R> u[9])
+{
+    // row 2 = conj(row 0 x row 1)
+    const cplx<R> c0 = u[1] * u[5] - u[2] * u[4];
+    const cplx<R> c1 = u[2] * u[3] - u[0] * u[5];
+    const cplx<R> c2 = u[0] * u[4] - u[1] * u[3];
+    u[6] = {c0.re, -c0.im};
+    u[7] = {c1.re, -c1.im};
+    u[8] = {c2.re, -c2.im};
+}
+
 template <typename S, typename R, bool NT = false>
 WCL_D void load_link(const void *base, int mu, int p, uint32_t h, uint32_t Vh, cplx<R> u[9])
 {
     const uint32_t mp = (uint32_t)(mu * 2 + p);
-    if constexpr (sizeof(S) == 8) {
+    if constexpr (std::is_same<S, R12f>::value) {
+        // float4 [4][2][3][Vh]: rows 0 and 1
+#pragma unroll
+        for (uint32_t k = 0; k < 3; k++) {
+            const float4 f = ldx<NT, float4>(base, ((mp * 3 + k) * Vh + h) * 16u);
+            u[2 * k] = {(R)f.x, (R)f.y};
+            u[2 * k + 1] = {(R)f.z, (R)f.w};
+        }
+        su3_third_row(u);
+    } else if constexpr (std::is_same<S, R12h>::value) {
+        // 8 halves [4][2][Vh] (complex 0..3) + 4 halves [4][2][Vh] (complex 4, 5)
+        const uint4 w = ldx<NT, uint4>(base, (mp * Vh + h) * 16u);
+        const uint2 v = ldx<NT, uint2>(base, 8u * Vh * 16u + (mp * Vh + h) * 8u);
+        const float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w), e = h2f2(v.x), f = h2f2(v.y);
+        u[0] = {(R)a.x, (R)a.y}; u[1] = {(R)b.x, (R)b.y}; u[2] = {(R)c.x, (R)c.y};
+        u[3] = {(R)d.x, (R)d.y}; u[4] = {(R)e.x, (R)e.y}; u[5] = {(R)f.x, (R)f.y};
+        su3_third_row(u);
+    } else if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t i = 0; i < 9; i++) {
             const double2 d = ldx<NT, double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
@@ -367,7 +408,23 @@ template <typename S, typename R>
 WCL_D void store_link(void *base, int mu, int p, uint32_t h, uint32_t Vh, const cplx<R> u[9])
 {
     const uint32_t mp = (uint32_t)(mu * 2 + p);
-    if constexpr (sizeof(S) == 8) {
+    if constexpr (std::is_same<S, R12f>::value) {
+#pragma unroll
+        for (uint32_t k = 0; k < 3; k++)
+            stf(base, ((mp * 3 + k) * Vh + h) * 16u,
+                make_float4((float)u[2 * k].re, (float)u[2 * k].im, (float)u[2 * k + 1].re, (float)u[2 * k + 1].im));
+    } else if constexpr (std::is_same<S, R12h>::value) {
+        uint4 w;
+        w.x = f22h((float)u[0].re, (float)u[0].im);
+        w.y = f22h((float)u[1].re, (float)u[1].im);
+        w.z = f22h((float)u[2].re, (float)u[2].im);
+        w.w = f22h((float)u[3].re, (float)u[3].im);
+        stf(base, (mp * Vh + h) * 16u, w);
+        uint2 v;
+        v.x = f22h((float)u[4].re, (float)u[4].im);
+        v.y = f22h((float)u[5].re, (float)u[5].im);
+        stf(base, 8u * Vh * 16u + (mp * Vh + h) * 8u, v);
+    } else if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t i = 0; i < 9; i++)
             stf(base, ((mp * 9 + i) * Vh + h) * 16u, make_double2((double)u[i].re, (double)u[i].im));
@@ -403,6 +460,7 @@ WCL_HD size_t clover_bytes(int S_size, size_t Vh) { return 2 * (S_size == 8 ? 57
 template <typename S, typename R, bool NT = false>
 WCL_D void load_clover(const void *base, int p, uint32_t h, uint32_t Vh, R c[72])
 {
+    static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t k = 0; k < 36; k++) {
@@ -430,6 +488,7 @@ WCL_D void load_clover(const void *base, int p, uint32_t h, uint32_t Vh, R c[72]
 template <typename S>
 WCL_D void store_clover(void *base, int p, uint32_t h, uint32_t Vh, const double c[72])
 {
+    static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t k = 0; k < 36; k++)
@@ -457,6 +516,7 @@ WCL_D void store_clover(void *base, int p, uint32_t h, uint32_t Vh, const double
 template <typename S, typename R>
 WCL_D void load_clover_half(const void *base, int p, uint32_t h, uint32_t Vh, int half, R c[36])
 {
+    static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
         for (uint32_t k = 0; k < 18; k++) {

@@ -7,10 +7,13 @@
 
 namespace wcl {
 
-// Storage precision codes.
-enum Prec { P64 = 64, P32 = 32, P16 = 16 };
+// Storage precision codes.  P32C / P16C: links as two rows (12 reals) in
+// FP32 / FP16, clover in FP32 / FP16; spinors never use these codes.
+enum Prec { P64 = 64, P32 = 32, P16 = 16, P32C = 33, P16C = 17 };
 
-inline int prec_bytes(int prec) { return prec == P64 ? 8 : prec == P32 ? 4 : 2; }
+inline int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 || prec == P32C) ? 4 : 2; }
+// bytes of one compressed link field (both parities, 4 directions)
+inline size_t link_bytes_c(int prec, size_t Vh) { return prec == P32C ? 24 * 16 * Vh : (8 * 16 + 8 * 8) * Vh; }
 
 // Epilogues of the hopping kernel; acc = H_{p,1-p} in (projectors swapped
 // when dagger):
@@ -64,6 +67,11 @@ hipError_t launch_unpack_spinor(const Geom &g, const void *eo, double *canon, hi
 // Canonical U [V][4][3][3] -> internal link fields (any null pointer skipped).
 hipError_t launch_ingest_gauge(const Geom &g, const double *canon, void *u64, void *u32, void *u16,
                                hipStream_t st);
+// FP64 links -> two-row FP32 (P32C) and FP16 (P16C) link fields.
+hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, hipStream_t st);
+// Per-workgroup maxima of the SU(3) defect of the FP64 links (|row2 -
+// conj(row0 x row1)|, |row norm - 1|, |<row0, row1>|) into partial[nblocks].
+hipError_t launch_su3_check(const Geom &g, const void *u64, double *partial, int nblocks, hipStream_t st);
 // Clover T and T^-1 (FP64 arithmetic) from the FP64 links, written in all
 // three precisions.  info_dev[0] counts sites whose 6x6 block lost positive
 // definiteness during inversion (a zero or negative pivot).

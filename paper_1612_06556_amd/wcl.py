@@ -85,6 +85,7 @@ def load():
     lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
+    lib.wcl_set_compression.argtypes = [_vp, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -114,6 +115,10 @@ def wcl_set_stream(h, stream):
 
 def wcl_set_gauge(h, U_ptr):
     _check(load().wcl_set_gauge(h, _vp(U_ptr)))
+
+
+def wcl_set_compression(h, enable):
+    _check(load().wcl_set_compression(h, int(enable)))
 
 
 def wcl_set_params(h, kappa, csw):
@@ -217,6 +222,11 @@ class Lattice:
         self._U = self._dev(U, (self.V, 4, 3, 3))
         self._sync_stream()
         wcl_set_gauge(self.h, self._U.data_ptr())
+
+    def set_compression(self, enable):
+        """Two-row (12-real) FP32/FP16 link storage; the links must be SU(3)."""
+        self._sync_stream()
+        wcl_set_compression(self.h, int(bool(enable)))
 
     def set_params(self, kappa, csw):
         self._sync_stream()
