@@ -6,7 +6,8 @@ Gaussian source (seed 2003).  One step is one pass of the whole hot path:
 gauge ingest and precision casts, clover build and inversion, then the solve
 of D x = b to a true FP64 residual of 1e-10 by the FP64 flexible BiCGStab
 preconditioned with the FP32 BiCGStab + even/odd + overlapped RAS (4^4
-cores, overlap 1, 4 MR steps).
+cores, overlap 1, 4 MR steps).  As in the paper's single-precision solver,
+the FP32 tier stores two rows of each SU(3) link and rebuilds the third.
 
 `value` is the step's sustained GFlop/s: the flops the library's kernels
 perform in the timed steps (1320 per hop site, 504 per clover site, 48 per
@@ -48,23 +49,123 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(U, psi, budget_s=15.0):
-    """The FP64 oracle's full-lattice D apply on the host cores (bounded sample)."""
+def cpu_baseline(U, psi, budget_s=12.0):
+    """The FP64 oracle's full-lattice D apply on the host cores (bounded
+    sample), then on one thread for a third of the budget."""
     import oracle
-    threads = oracle.set_threads(0)
-    orc = oracle.Oracle(DIMS, -1, KAPPA, CSW, U)
     V = int(np.prod(DIMS))
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        orc.D(psi)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 400:
-            break
+
+    def run(budget):
+        orc = oracle.Oracle(DIMS, -1, KAPPA, CSW, U)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            orc.D(psi)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget or n >= 400:
+                return n, el
+
+    threads = oracle.set_threads(0)
+    n, el = run(budget_s)
     flops = n * V * (1320.0 + 504.0 + 48.0)
+    oracle.set_threads(1)
+    n1, el1 = run(budget_s / 3)
+    oracle.set_threads(threads)
     return {"value": round(flops / el / 1e9, 3), "unit": "GFlop/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full-lattice FP64 D applications at 24^3x32 (1872 flop/site), {el:.1f} s"}
+            "sample": f"{n} full-lattice FP64 D applications at 24^3x32 (1872 flop/site), {el:.1f} s",
+            "single_thread_value": round(n1 * V * 1872.0 / el1 / 1e9, 3)}
+
+
+def _median_ms(fn, trials=5):
+    return float(np.median([fn() for _ in range(trials)]))
+
+
+def _rate(ms, Vh, flop_site, bytes_site):
+    gbs = bytes_site * Vh / ms / 1e6
+    return {"us": round(ms * 1e3, 2), "GFlop/s": round(flop_site * Vh / ms / 1e6, 1), "GB/s": round(gbs, 1),
+            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
+    """Standalone kernels (median of 5 trials of 200 launches, cold = 4
+    rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set),
+    the copy ceiling, the paper's long lattice, and time-to-solution
+    variants against the plain FP64 solve."""
+    out = {}
+    hop, clov = {}, {}
+    for comp in (0, 1):
+        lat.set_compression(comp)
+        for prec in (32, 16):
+            link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
+            for copies, tag in ((4, "cold"), (1, "hot")):
+                ms = _median_ms(lambda: lat.bench_hop(prec, 200, copies))
+                name = f"fp{prec}{'_r12' if comp else ''}_{tag}"
+                hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
+                if not comp:
+                    ms = _median_ms(lambda: lat.bench_clover(prec, 200, copies))
+                    clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
+    lat.set_compression(1)
+    out["hop_standalone"] = hop
+    out["clover_standalone"] = clov
+    # measured streaming ceiling: device-to-device copy of 2 x 1 GiB
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 4 / (time.perf_counter() - t1) / 1e9
+    del src, dst
+    out["copy_ceiling_GBps"] = round(copy_gbs, 1)
+    out["hop_fp32_cold_frac_of_copy"] = round(hop["fp32_cold"]["GB/s"] / copy_gbs, 3)
+    out["hop_fp32_cold_vs_paper_knc_200gflops"] = round(hop["fp32_cold"]["GFlop/s"] / PAPER_KNC_HOP_GFLOPS, 1)
+    # the paper's long single-card lattice: FP32 links alone (382 MB) exceed the Infinity Cache
+    dl = (24, 24, 24, 96)
+    long_lat = wcl.Lattice(dl, -1)
+    long_lat.set_gauge(torch.from_numpy(np.tile(U, (3, 1, 1, 1))).cuda())
+    vl = int(np.prod(dl)) // 2
+    long = {}
+    for comp in (0, 1):
+        long_lat.set_compression(comp)
+        for prec in (32, 16):
+            link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
+            ms = _median_ms(lambda: long_lat.bench_hop(prec, 200, 1))
+            long[f"fp{prec}{'_r12' if comp else ''}"] = _rate(ms, vl, 1320, 8 * link_b + 192)
+    long_lat.close()
+    out["hop_24x24x24x96"] = long
+    # time-to-solution variants (one warm run each, median of 3)
+    sol = {}
+    variants = (("mixed_ras_fp32", opts, 1),
+                ("mixed_ras_fp32_full_links", opts, 0),
+                ("mixed_ras_fp32_graph", dict(opts, use_graph=1), 1),
+                ("mixed_ras_fp16", dict(opts, inner_prec=16), 1),
+                ("mixed_noras_fp32", dict(opts, use_ras=0), 1),
+                ("mixed_noras_fp32_full_links", dict(opts, use_ras=0), 0),
+                ("mixed_noras_fp32_graph", dict(opts, use_ras=0, use_graph=1), 1),
+                ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16), 1),
+                ("mixed_noras_fp16_graph", dict(opts, use_ras=0, inner_prec=16, use_graph=1), 1),
+                ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000), 0))
+    for name, kw, comp in variants:
+        lat.set_compression(comp)
+        lat.solve(gb, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            _, info, _ = lat.solve(gb, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        sol[name] = {"ms": round(float(np.median(ts)) * 1e3, 2), "outer": info["outer_iters"],
+                     "inner": info["inner_iters_total"], "true_relres": info["true_relres"]}
+    lat.set_compression(1)
+    base = sol["plain_fp64"]["ms"]
+    for k in sol:
+        sol[k]["speedup_vs_plain_fp64"] = round(base / sol[k]["ms"], 2)
+    out["time_to_solution"] = sol
+    return out
 
 
 def main():
@@ -93,6 +194,9 @@ def main():
     gU = torch.from_numpy(U).cuda()
     gb = torch.from_numpy(b).cuda()
     lat = wcl.Lattice(DIMS, -1)
+    # the paper's single-precision solver keeps two of the three SU(3) rows
+    # (the third is rebuilt); the FP64 outer work reads full links
+    lat.set_compression(1)
     lat.set_gauge(gU)
     lat.set_params(KAPPA, CSW)
 
@@ -139,7 +243,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     roof["kernel"] = {"hop": "k_hop (even/odd hopping with fused clover epilogues)",
-                      "ras": "k_ras (RAS block solver)", "clover": "k_clover"}[dom]
+                      "ras": "k_ras<R12f, 648> (RAS block solver, two-row FP32 links)", "clover": "k_clover"}[dom]
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = round(d["ms"] * 1e3 / max(d["launches"], 1), 2)
     roof["share_of_gpu_time"] = round(d["ms"] / sum(s["ms"] for s in stats.values()), 3)
@@ -155,7 +259,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "24^3x32 Wilson-Clover solve to 1e-10: FP64 flexible BiCGStab + FP32 "
-                               "RAS-BiCGStab (4^4 cores, overlap 1, 4 MR), incl. gauge ingest and clover build",
+                               "RAS-BiCGStab (4^4 cores, overlap 1, 4 MR, two-row SU(3) links), incl. gauge "
+                               "ingest and clover build",
                    "lattice": "24x24x24x32", "kappa": KAPPA, "csw": CSW, "t_bc": "antiperiodic",
                    "gauge": "reunitarised exp(0.3 i H), seed 1003", "source": "Gaussian, seed 2003",
                    "tuning": tuning},
@@ -166,50 +271,7 @@ def main():
     }
 
     if not args.no_extras:
-        # standalone hopping kernel: cold (4 rotating field sets, > 256 MB MALL) and hot (1 set)
-        hop = {}
-        for prec in (32, 16):
-            for copies, tag in ((4, "cold"), (1, "hot")):
-                ms = lat.bench_hop(prec, 200, copies)
-                byts = (576 if prec == 32 else 288) + 192
-                hop[f"fp{prec}_{tag}"] = {"us": round(ms * 1e3, 2), "GFlop/s": round(1320 * Vh / ms / 1e6, 1),
-                                          "GB/s": round(byts * Vh / ms / 1e6, 1),
-                                          "frac_hbm": round(byts * Vh / ms / 1e6 / HBM_PEAK_GBS, 4)}
-        out["hop_standalone"] = hop
-        # measured streaming ceiling: device-to-device copy of 2 x 1 GiB
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(10):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        copy_gbs = 10 * 2 * src.numel() * 4 / (time.perf_counter() - t1) / 1e9
-        out["copy_ceiling_GBps"] = round(copy_gbs, 1)
-        out["hop_fp32_cold_frac_of_copy"] = round(hop["fp32_cold"]["GB/s"] / copy_gbs, 3)
-        del src, dst
-        out["hop_fp32_cold_vs_paper_knc_200gflops"] = round(hop["fp32_cold"]["GFlop/s"] / PAPER_KNC_HOP_GFLOPS, 1)
-        # time-to-solution variants (one warm run each)
-        sol = {}
-        for name, kw in (("mixed_ras_fp32", opts),
-                         ("mixed_ras_fp32_graph", dict(opts, use_graph=1)),
-                         ("mixed_noras_fp32", dict(opts, use_ras=0)),
-                         ("mixed_noras_fp32_graph", dict(opts, use_ras=0, use_graph=1)),
-                         ("mixed_ras_fp16", dict(opts, inner_prec=16)),
-                         ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
-                         ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):
-            lat.solve(gb, **kw)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, info, _ = lat.solve(gb, **kw)
-            torch.cuda.synchronize()
-            sol[name] = {"ms": round((time.perf_counter() - t1) * 1e3, 2), "outer": info["outer_iters"],
-                         "inner": info["inner_iters_total"], "true_relres": info["true_relres"]}
-        base = sol["plain_fp64"]["ms"]
-        for k in sol:
-            sol[k]["speedup_vs_plain_fp64"] = round(base / sol[k]["ms"], 2)
-        out["time_to_solution"] = sol
+        out.update(extras(lat, U, gb, opts, Vh, torch, synth, wcl))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U, b)

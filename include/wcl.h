@@ -153,6 +153,10 @@ int wcl_grad(wcl_ctx *ctx, const double *x_dev, const double *y_dev, double *gU_
  * of links and spinors (copies >= 1; more copies defeat the 256 MB Infinity
  * Cache).  *ms_per_call receives the mean launch time from HIP events. */
 int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
+/* Time the standalone clover apply out_e = T_ee^-1 in_e (FP32 or FP16
+ * clover, FP32 spinors), the 504-flop-per-site half of the Schur operator,
+ * with the same protocol.  WCL_ESTATE before wcl_set_params. */
+int wcl_bench_clover(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
 
 /* Kernel-class profiling on the context's stream: with profiling enabled,
  * every launch of the classes below is bracketed by HIP events and its

@@ -1218,37 +1218,11 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
 }
 
 // ===========================================================================
-extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double *ms)
+namespace {
+// Mean event time of `reps` launches (after 10 warm-ups) rotating over copies.
+template <typename F>
+int time_launches(wcl_ctx *c, int reps, int copies, F launch, double *ms)
 {
-    if (!c || !ms) return fail(WCL_EINVAL, "null argument");
-    if (!c->have_gauge) return fail(WCL_ESTATE, "wcl_bench_hop before wcl_set_gauge");
-    if (prec != 32 && prec != 16) return fail(WCL_EINVAL, "bench prec must be 32 or 16");
-    if (reps < 1 || copies < 1 || copies > 32) return fail(WCL_EINVAL, "reps >= 1 and 1 <= copies <= 32 required");
-    const size_t Vh = c->Vh;
-    const int lb = prec_bytes(prec), ep = eff_lprec(c, prec);
-    const size_t lbytes = ep == prec ? link_bytes(lb, Vh) : link_bytes_c(ep, Vh), sbytes = spinor_bytes(4, Vh);
-    std::vector<void *> lk(copies), in(copies), out(copies);
-    for (int k = 0; k < copies; k++) {
-        if (k == 0) lk[k] = links_for(c, prec);
-        else {
-            CHK(wsget(c, S_BENCH + 3 * k, lbytes, &lk[k]));
-            HIPCHK(hipMemcpyAsync(lk[k], lk[0], lbytes, hipMemcpyDeviceToDevice, c->st));
-        }
-        CHK(wsget(c, S_BENCH + 3 * k + 1, sbytes, &in[k]));
-        CHK(wsget(c, S_BENCH + 3 * k + 2, sbytes, &out[k]));
-        // deterministic, non-trivial input: copy the FP32 links' first reals
-        HIPCHK(hipMemcpyAsync(in[k], c->U32, sbytes, hipMemcpyDeviceToDevice, c->st));
-    }
-    auto launch = [&](int k) -> int {
-        HopLaunch L = hop_base(c, prec, P32);
-        L.links = lk[k];
-        L.mode = HOP;
-        L.p = 0;
-        L.in = in[k];
-        L.out = out[k];
-        HIPCHK(launch_hop(L, c->st));
-        return WCL_OK;
-    };
     for (int i = 0; i < 10; i++) CHK(launch(i % copies));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1263,6 +1237,69 @@ extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double 
     (void)hipEventDestroy(e1);
     *ms = (double)t / reps;
     return WCL_OK;
+}
+
+int bench_args(wcl_ctx *c, int prec, int reps, int copies, const double *ms, bool need_params, const char *what)
+{
+    if (!c || !ms) return fail(WCL_EINVAL, "null argument");
+    if (!(need_params ? c->have_params : c->have_gauge))
+        return fail(WCL_ESTATE, std::string(what) + (need_params ? " before wcl_set_params" : " before wcl_set_gauge"));
+    if (prec != 32 && prec != 16) return fail(WCL_EINVAL, "bench prec must be 32 or 16");
+    if (reps < 1 || copies < 1 || copies > 32) return fail(WCL_EINVAL, "reps >= 1 and 1 <= copies <= 32 required");
+    return WCL_OK;
+}
+}  // namespace
+
+extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double *ms)
+{
+    CHK(bench_args(c, prec, reps, copies, ms, false, "wcl_bench_hop"));
+    const size_t Vh = c->Vh;
+    const int lb = prec_bytes(prec), ep = eff_lprec(c, prec);
+    const size_t lbytes = ep == prec ? link_bytes(lb, Vh) : link_bytes_c(ep, Vh), sbytes = spinor_bytes(4, Vh);
+    std::vector<void *> lk(copies), in(copies), out(copies);
+    for (int k = 0; k < copies; k++) {
+        if (k == 0) lk[k] = links_for(c, ep);
+        else {
+            CHK(wsget(c, S_BENCH + 3 * k, lbytes, &lk[k]));
+            HIPCHK(hipMemcpyAsync(lk[k], lk[0], lbytes, hipMemcpyDeviceToDevice, c->st));
+        }
+        CHK(wsget(c, S_BENCH + 3 * k + 1, sbytes, &in[k]));
+        CHK(wsget(c, S_BENCH + 3 * k + 2, sbytes, &out[k]));
+        // deterministic, non-trivial input: copy the FP32 links' first reals
+        HIPCHK(hipMemcpyAsync(in[k], c->U32, sbytes, hipMemcpyDeviceToDevice, c->st));
+    }
+    return time_launches(c, reps, copies, [&](int k) -> int {
+        HopLaunch L = hop_base(c, prec, P32);
+        L.links = lk[k];
+        L.mode = HOP;
+        L.p = 0;
+        L.in = in[k];
+        L.out = out[k];
+        HIPCHK(launch_hop(L, c->st));
+        return WCL_OK;
+    }, ms);
+}
+
+extern "C" int wcl_bench_clover(wcl_ctx *c, int prec, int reps, int copies, double *ms)
+{
+    CHK(bench_args(c, prec, reps, copies, ms, true, "wcl_bench_clover"));
+    const size_t Vh = c->Vh;
+    const size_t cbytes = clover_bytes(prec_bytes(prec), Vh), sbytes = spinor_bytes(4, Vh);
+    std::vector<void *> cl(copies), in(copies), out(copies);
+    for (int k = 0; k < copies; k++) {
+        if (k == 0) cl[k] = clovinv_for(c, prec);
+        else {
+            CHK(wsget(c, S_BENCH + 3 * k, cbytes, &cl[k]));
+            HIPCHK(hipMemcpyAsync(cl[k], cl[0], cbytes, hipMemcpyDeviceToDevice, c->st));
+        }
+        CHK(wsget(c, S_BENCH + 3 * k + 1, sbytes, &in[k]));
+        CHK(wsget(c, S_BENCH + 3 * k + 2, sbytes, &out[k]));
+        HIPCHK(hipMemcpyAsync(in[k], c->U32, sbytes, hipMemcpyDeviceToDevice, c->st));
+    }
+    return time_launches(c, reps, copies, [&](int k) -> int {
+        HIPCHK(launch_clover(c->g, prec, P32, 0, cl[k], in[k], out[k], c->st));
+        return WCL_OK;
+    }, ms);
 }
 
 extern "C" int wcl_grad(wcl_ctx *c, const double *x, const double *y, double *gU, double *gk)

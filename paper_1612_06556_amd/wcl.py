@@ -80,6 +80,7 @@ def load():
                               ctypes.POINTER(wcl_solve_info)]
     lib.wcl_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
     lib.wcl_bench_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.wcl_bench_clover.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.wcl_destroy.argtypes = [_vp]
     lib.wcl_profile.argtypes = [_vp, ctypes.c_int]
     lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
@@ -160,6 +161,12 @@ def wcl_grad(h, x_ptr, y_ptr, gU_ptr):
 def wcl_bench_hop(h, prec, reps, copies):
     ms = ctypes.c_double(0.0)
     _check(load().wcl_bench_hop(h, int(prec), int(reps), int(copies), ctypes.byref(ms)))
+    return ms.value
+
+
+def wcl_bench_clover(h, prec, reps, copies):
+    ms = ctypes.c_double(0.0)
+    _check(load().wcl_bench_clover(h, int(prec), int(reps), int(copies), ctypes.byref(ms)))
     return ms.value
 
 
@@ -278,6 +285,10 @@ class Lattice:
     def bench_hop(self, prec=32, reps=100, copies=1):
         self._sync_stream()
         return wcl_bench_hop(self.h, prec, reps, copies)
+
+    def bench_clover(self, prec=32, reps=100, copies=1):
+        self._sync_stream()
+        return wcl_bench_clover(self.h, prec, reps, copies)
 
     def close(self):
         if getattr(self, "h", None):

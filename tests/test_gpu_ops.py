@@ -137,3 +137,15 @@ def test_ras_op_launch_accounting():
     expect = (hops * 168 + 1296 * 504 + 648 * 240) * 4 * 16
     assert st["launches"] == 1
     assert st["flops"] == expect
+
+
+def test_bench_entry_points():
+    """wcl_bench_hop / wcl_bench_clover run on rotating copies and leave the
+    context's fields intact (D still matches the oracle afterwards)."""
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    for prec in (32, 16):
+        assert lat.bench_hop(prec, 5, 3) > 0
+        assert lat.bench_clover(prec, 5, 3) > 0
+    psi = synth.gaussian_spinor(dims, 41)
+    assert rel(to_host(lat.apply(to_gpu(psi), prec=32)), orc.D(psi)) <= 1e-6
