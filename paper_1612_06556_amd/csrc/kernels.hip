@@ -431,10 +431,10 @@ struct HopArgs {
 // link of hop k+1 are in flight while hop k is computed; a scheduling barrier
 // after each hop keeps the compiler from hoisting further loads (which would
 // raise the register count and lower the occupancy).
-template <typename R>
+template <typename SL, typename R>
 struct HopStage {
     cplx<R> psi[12];
-    cplx<R> u[9];
+    LinkRaw<SL> u;   // as loaded; decoded when the hop is computed
     R sign;
 };
 
@@ -455,7 +455,7 @@ WCL_D void pipeline_fence(cplx<R> acc[12], uint32_t &hn, uint32_t &h)
 }
 
 template <typename SL, typename SS, int K, bool NT, typename R>
-WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, HopStage<R> &st,
+WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, HopStage<SL, R> &st,
                     cplx<R> acc[12])
 {
     constexpr int MU = K >> 1;
@@ -466,30 +466,31 @@ WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in
     uint32_t h = h0;
     pipeline_fence(acc, hn, h);
     load_spinor<SS, R>(in, hn, Vh, st.psi);
-    if (FWD) load_link<SL, R, NT>(a.links, MU, a.p, h, Vh, st.u);
-    else load_link<SL, R, NT>(a.links, MU, 1 - a.p, hn, Vh, st.u);
+    if (FWD) load_link_raw<SL, NT>(a.links, MU, a.p, h, Vh, st.u);
+    else load_link_raw<SL, NT>(a.links, MU, 1 - a.p, hn, Vh, st.u);
     st.sign = R(1);
     if (MU == 3 && g.tbc < 0 && s.x[3] == (FWD ? g.L[3] - 1 : 0)) st.sign = R(-1);
 }
 
 // forward: (1 - SG g_mu) U_mu(x) psi(x+mu);  backward: (1 + SG g_mu) U_mu(x-mu)^dag psi(x-mu)
-template <int K, int SG, typename R>
-WCL_D void hop_compute(const HopStage<R> &st, cplx<R> acc[12])
+template <int K, int SG, typename SL, typename R>
+WCL_D void hop_compute(const HopStage<SL, R> &st, cplx<R> acc[12])
 {
     constexpr int MU = K >> 1;
     constexpr bool FWD = (K & 1) == 0;
     constexpr int S = FWD ? -SG : SG;
-    cplx<R> hh[6], uh[6];
+    cplx<R> hh[6], uh[6], u[9];
     project<MU, S, R>(st.psi, hh);
 #pragma unroll
     for (int k = 0; k < 6; k++) hh[k] = st.sign * hh[k];
-    if (FWD) su3_mul(st.u, hh, uh);
-    else su3_dag_mul(st.u, hh, uh);
+    expand_link<SL, R>(st.u, u);
+    if (FWD) su3_mul(u, hh, uh);
+    else su3_dag_mul(u, hh, uh);
     accumulate<MU, S, R>(acc, uh);
 }
 
 template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
-WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
+WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<SL, R> st[D],
                         cplx<R> acc[12])
 {
     if constexpr (K < D - 1) {
@@ -500,12 +501,12 @@ WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char 
 
 // hop K is computed while the operands of hop K + D - 1 are in flight
 template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
-WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<R> st[D],
+WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<SL, R> st[D],
                         cplx<R> acc[12])
 {
     if constexpr (K < 8) {
         if constexpr (K + D - 1 < 8) hop_load<SL, SS, K + D - 1, NT, R>(a, s, h, in, st[(K + D - 1) % D], acc);
-        hop_compute<K, SG, R>(st[K % D], acc);
+        hop_compute<K, SG, SL, R>(st[K % D], acc);
         hop_pipeline<SL, SS, SG, D, K + 1, NT, R>(a, s, h, in, st, acc);
     }
 }
@@ -534,7 +535,7 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     cplx<R> acc[12];
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = {R(0), R(0)};
-    HopStage<R> st[DEPTH];
+    HopStage<SL, R> st[DEPTH];
     hop_prologue<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
     hop_pipeline<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
 

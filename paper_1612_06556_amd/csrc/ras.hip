@@ -49,10 +49,12 @@ WCL_D void ext_to_global(const Geom &g, int mu, int b, int a, int delta, int &ti
 }
 
 // One hop of the block operator: the neighbour spinor comes from LDS, the
-// link from global memory; a neighbour outside the extended block is replaced
-// by the site itself with weight 0 (Dirichlet cut without divergent branches).
+// link from global memory (held encoded until the hop is computed); a
+// neighbour outside the extended block is replaced by the site itself with
+// weight 0 (Dirichlet cut without divergent branches).
+template <typename SL>
 struct RasStage {
-    cplx<float> u[9];
+    LinkRaw<SL> u;
     uint32_t ln;   // local half index of the neighbour (other parity)
     float w;       // 0 (outside the block), else the t boundary sign
 };
@@ -67,34 +69,40 @@ WCL_D void ras_fence(cplx<float> acc[12], uint32_t &a, uint32_t &b)
                    "+v"(acc[10].re), "+v"(acc[10].im), "+v"(acc[11].re), "+v"(acc[11].im), "+v"(a), "+v"(b));
 }
 
-// nb: packed neighbour table, entry K = forward (K even) / backward (K odd)
-// in direction K/2: the local half index of the other parity, 0xffff if the
-// neighbour is outside the block.  The link of hop K is prefetched (global
-// memory, long latency) one hop ahead; the neighbour spinor is read from LDS
-// when the hop is computed.
+// Per-thread constants of one parity's half of the block operator.
+struct RasSite {
+    uint32_t g;      // global half index of the site
+    uint32_t nb[4];  // packed neighbour table (see ras_load)
+    float sf, sb;    // t boundary signs of the forward / backward t hop
+};
+
+// nb: entry K = forward (K even) / backward (K odd) in direction K/2: the
+// local half index of the other parity, 0xffff if the neighbour is outside
+// the block.  The link of hop K is loaded (global memory, long latency) one
+// hop ahead; the neighbour spinor is read from LDS when the hop is computed.
 template <typename SL, int K>
-WCL_D void ras_load(const void *links, int q, uint32_t gq, uint32_t Vh, uint32_t t, const uint32_t nb[4],
-                    const int *gnb, float sf, float sb, RasStage &st, cplx<float> acc[12])
+WCL_D void ras_load(const void *links, int q, const RasSite &S, uint32_t Vh, uint32_t t, const int *gnb,
+                    RasStage<SL> &st, cplx<float> acc[12])
 {
     constexpr int MU = K >> 1;
     constexpr bool FWD = (K & 1) == 0;
-    uint32_t ln = (nb[MU] >> (FWD ? 0 : 16)) & 0xffffu;
+    uint32_t ln = (S.nb[MU] >> (FWD ? 0 : 16)) & 0xffffu;
     const bool in = ln != 0xffffu;
     if (!in) ln = t;                       // any valid site; its weight is 0
-    uint32_t gl = FWD ? gq : (uint32_t)gnb[ln];
+    uint32_t gl = FWD ? S.g : (uint32_t)gnb[ln];
     ras_fence(acc, ln, gl);
-    load_link<SL, float>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
+    load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
     st.ln = ln;
-    st.w = in ? (MU == 3 ? (FWD ? sf : sb) : 1.f) : 0.f;
+    st.w = in ? (MU == 3 ? (FWD ? S.sf : S.sb) : 1.f) : 0.f;
 }
 
-template <int K, int NE>
-WCL_D void ras_compute(const RasStage &st, const float2 *src, cplx<float> acc[12])
+template <typename SL, int K, int NE>
+WCL_D void ras_compute(const RasStage<SL> &st, const float2 *src, cplx<float> acc[12])
 {
     constexpr int MU = K >> 1;
     constexpr bool FWD = (K & 1) == 0;
     constexpr int S = FWD ? -1 : 1;
-    cplx<float> psi[12], hh[6], uh[6];
+    cplx<float> psi[12], hh[6], uh[6], u[9];
 #pragma unroll
     for (int c = 0; c < 12; c++) {
         const float2 v = src[c * NE + st.ln];
@@ -103,49 +111,76 @@ WCL_D void ras_compute(const RasStage &st, const float2 *src, cplx<float> acc[12
     project<MU, S, float>(psi, hh);
 #pragma unroll
     for (int k = 0; k < 6; k++) hh[k] = st.w * hh[k];
-    if (FWD) su3_mul(st.u, hh, uh);
-    else su3_dag_mul(st.u, hh, uh);
+    expand_link<SL, float>(st.u, u);
+    if (FWD) su3_mul(u, hh, uh);
+    else su3_dag_mul(u, hh, uh);
     accumulate<MU, S, float>(acc, uh);
 }
 
-// acc = (block hop of the other parity, read from src) at this thread's site
-template <typename SL, int NE>
-WCL_D void ras_hop(const void *links, int q, uint32_t gq, uint32_t Vh, uint32_t t, const uint32_t nb[4],
-                   const int *gnb, const float2 *src, float sf, float sb, cplx<float> acc[12])
+// The first two link loads of a pass, then acc = 0.  The loads' fences take
+// the previous pass's accumulator, so they wait for the work that consumed
+// it.  (Issuing them before the barrier that ends the previous pass does not
+// pay: the barrier waits for every outstanding load, and the longer live
+// ranges spill.)
+template <typename SL>
+WCL_D void ras_hop_start(const void *links, int q, const RasSite &S, uint32_t Vh, uint32_t t, const int *gnb,
+                         RasStage<SL> &A, RasStage<SL> &B, cplx<float> acc[12])
 {
-    RasStage A, B;
+    ras_load<SL, 0>(links, q, S, Vh, t, gnb, A, acc);
+    ras_load<SL, 1>(links, q, S, Vh, t, gnb, B, acc);
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = {0.f, 0.f};
-    ras_load<SL, 0>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
-    ras_load<SL, 1>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
-    ras_compute<0, NE>(A, src, acc);
-    ras_load<SL, 2>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
-    ras_compute<1, NE>(B, src, acc);
-    ras_load<SL, 3>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
-    ras_compute<2, NE>(A, src, acc);
-    ras_load<SL, 4>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
-    ras_compute<3, NE>(B, src, acc);
-    ras_load<SL, 5>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
-    ras_compute<4, NE>(A, src, acc);
-    ras_load<SL, 6>(links, q, gq, Vh, t, nb, gnb, sf, sb, A, acc);
-    ras_compute<5, NE>(B, src, acc);
-    ras_load<SL, 7>(links, q, gq, Vh, t, nb, gnb, sf, sb, B, acc);
-    ras_compute<6, NE>(A, src, acc);
-    ras_compute<7, NE>(B, src, acc);
 }
 
-// out = A acc, one chirality block at a time; each block's loads wait for
-// the preceding work (fence), which keeps 36 clover reals live, not 72.
-template <typename SL>
-WCL_D void ras_clover(const void *clov, int q, uint32_t gq, uint32_t Vh, cplx<float> acc[12], cplx<float> out[12])
+// acc = (block hop of the other parity, read from src) at this thread's
+// site, then out = A^-1 acc.  Each clover half's loads wait for the
+// preceding work (fence), which keeps 36 clover reals live, not 72; with an
+// FP16 clover (18 registers a half) the first half is loaded while the last
+// hop is computed (with FP32 the extra registers spill).
+template <typename SL, int NE>
+WCL_D void ras_hop_finish(const void *links, const void *clov, int q, const RasSite &S, uint32_t Vh, uint32_t t,
+                          const int *gnb, const float2 *src, RasStage<SL> &A, RasStage<SL> &B, cplx<float> acc[12],
+                          cplx<float> out[12])
 {
-#pragma unroll
-    for (int half = 0; half < 2; half++) {
-        uint32_t gc = gq, dummy = 0;
+    using CS = typename ClovS<SL>::T;
+    ras_compute<SL, 0, NE>(A, src, acc);
+    ras_load<SL, 2>(links, q, S, Vh, t, gnb, A, acc);
+    ras_compute<SL, 1, NE>(B, src, acc);
+    ras_load<SL, 3>(links, q, S, Vh, t, gnb, B, acc);
+    ras_compute<SL, 2, NE>(A, src, acc);
+    ras_load<SL, 4>(links, q, S, Vh, t, gnb, A, acc);
+    ras_compute<SL, 3, NE>(B, src, acc);
+    ras_load<SL, 5>(links, q, S, Vh, t, gnb, B, acc);
+    ras_compute<SL, 4, NE>(A, src, acc);
+    ras_load<SL, 6>(links, q, S, Vh, t, gnb, A, acc);
+    ras_compute<SL, 5, NE>(B, src, acc);
+    ras_load<SL, 7>(links, q, S, Vh, t, gnb, B, acc);
+    ras_compute<SL, 6, NE>(A, src, acc);
+    if constexpr (sizeof(CS) == 2) {
+        ClovHalfRaw<CS> c0;
+        {
+            uint32_t gc = S.g, dummy = 0;
+            ras_fence(acc, gc, dummy);
+            load_clover_half_raw<CS>(clov, q, gc, Vh, 0, c0);
+        }
+        ras_compute<SL, 7, NE>(B, src, acc);
+        float cl[36];
+        expand_clover_half<CS, float>(c0, 0, cl);
+        clover_mul_half(cl, acc, out);
+    } else {
+        ras_compute<SL, 7, NE>(B, src, acc);
+        uint32_t gc = S.g, dummy = 0;
         ras_fence(acc, gc, dummy);
         float cl[36];
-        load_clover_half<typename ClovS<SL>::T, float>(clov, q, gc, Vh, half, cl);
-        clover_mul_half(cl, acc + 6 * half, out + 6 * half);
+        load_clover_half<CS, float>(clov, q, gc, Vh, 0, cl);
+        clover_mul_half(cl, acc, out);
+    }
+    {
+        uint32_t gc = S.g, dummy = 0;
+        ras_fence(acc, gc, dummy);
+        float cl[36];
+        load_clover_half<CS, float>(clov, q, gc, Vh, 1, cl);
+        clover_mul_half(cl, acc + 6, out + 6);
     }
 }
 
@@ -228,11 +263,11 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     // this thread owns local half index t on both parities
     const uint32_t t = threadIdx.x;
     const bool active = (int)t < Ne;
-    uint32_t nbE[4], nbO[4];
-    float sfE = 1.f, sbE = 1.f, sfO = 1.f, sbO = 1.f;
+    RasSite SE, SO;
+    SE.sf = SE.sb = SO.sf = SO.sb = 1.f;
     bool core = false;
 #pragma unroll
-    for (int k = 0; k < 4; k++) { nbE[k] = 0xffffffffu; nbO[k] = 0xffffffffu; }
+    for (int k = 0; k < 4; k++) { SE.nb[k] = 0xffffffffu; SO.nb[k] = 0xffffffffu; }
     if (active) {
 #pragma unroll
         for (int q = 0; q < 2; q++) {
@@ -246,49 +281,50 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             const int ev[4] = {e0, e1, e2, e3};
             const int lin = a0 + e0 * (a1 + e1 * (a2 + e2 * a3));
             int st = 1;
-            uint32_t *nb = q == 0 ? nbE : nbO;
+            RasSite &S = q == 0 ? SE : SO;
 #pragma unroll
             for (int mu = 0; mu < 4; mu++) {
                 const uint32_t f = (av[mu] + 1 < ev[mu]) ? (uint32_t)((lin + st) >> 1) : 0xffffu;
                 const uint32_t bk = (av[mu] >= 1) ? (uint32_t)((lin - st) >> 1) : 0xffffu;
-                nb[mu] = f | (bk << 16);
+                S.nb[mu] = f | (bk << 16);
                 st *= ev[mu];
             }
             int tile, loc, xt;
             ext_to_global(g, 3, bc[3], a3, d, tile, loc, xt);
-            const float sf = (g.tbc < 0 && xt == g.L[3] - 1) ? -1.f : 1.f;
-            const float sb = (g.tbc < 0 && xt == 0) ? -1.f : 1.f;
+            S.sf = (g.tbc < 0 && xt == g.L[3] - 1) ? -1.f : 1.f;
+            S.sb = (g.tbc < 0 && xt == 0) ? -1.f : 1.f;
             if (q == 0) {
-                sfE = sf; sbE = sb;
                 core = true;
 #pragma unroll
                 for (int mu = 0; mu < 4; mu++)
                     if (av[mu] < d || av[mu] >= d + g.B[mu]) core = false;
-            } else {
-                sfO = sf; sbO = sb;
             }
         }
     }
     __syncthreads();
-    const uint32_t gE = active ? (uint32_t)gh[t] : 0u;
-    const uint32_t gO = active ? (uint32_t)gh[MAXNE + t] : 0u;
+    SE.g = active ? (uint32_t)gh[t] : 0u;
+    SO.g = active ? (uint32_t)gh[MAXNE + t] : 0u;
     const uint32_t Vh = g.Vh;
 
     // r = the input on the even block sites (zero start: z = 0, r = rhs)
     if (active) {
         cplx<float> r[12];
-        load_spinor<float, float>(rin, gE, Vh, r);
+        load_spinor<float, float>(rin, SE.g, Vh, r);
 #pragma unroll
         for (int c = 0; c < 12; c++) sE[c * MAXNE + t] = make_float2(r[c].re, r[c].im);
     }
 
+    RasStage<SL> A, B;
+    cplx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = {0.f, 0.f};
     for (int it = 0; it < a.iters; it++) {
         __syncthreads();
         // odd half: y = A_oo^-1 H_oe r on the odd block sites
         if (active) {
-            cplx<float> acc[12], y[12];
-            ras_hop<SL, MAXNE>(a.links, 1, gO, Vh, t, nbO, gh, sE, sfO, sbO, acc);
-            ras_clover<SL>(a.clov_inv, 1, gO, Vh, acc, y);
+            cplx<float> y[12];
+            ras_hop_start<SL>(a.links, 1, SO, Vh, t, gh, A, B, acc);
+            ras_hop_finish<SL, MAXNE>(a.links, a.clov_inv, 1, SO, Vh, t, gh, sE, A, B, acc, y);
 #pragma unroll
             for (int c = 0; c < 12; c++) sO[c * MAXNE + t] = make_float2(y[c].re, y[c].im);
         }
@@ -297,9 +333,9 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
         cplx<float> qv[12];
         double dots[3] = {0.0, 0.0, 0.0};
         if (active) {
-            cplx<float> acc[12], w[12];
-            ras_hop<SL, MAXNE>(a.links, 0, gE, Vh, t, nbE, gh + MAXNE, sO, sfE, sbE, acc);
-            ras_clover<SL>(a.clov_inv, 0, gE, Vh, acc, w);
+            cplx<float> w[12];
+            ras_hop_start<SL>(a.links, 0, SE, Vh, t, gh + MAXNE, A, B, acc);
+            ras_hop_finish<SL, MAXNE>(a.links, a.clov_inv, 0, SE, Vh, t, gh + MAXNE, sO, A, B, acc, w);
             float qr = 0.f, qi = 0.f, qq = 0.f;
 #pragma unroll
             for (int c = 0; c < 12; c++) {
@@ -325,7 +361,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 #pragma unroll
                     for (int c = 0; c < 12; c++) z[c] = {0.f, 0.f};
                 } else {
-                    load_spinor<float, float>(rout, gE, Vh, z);
+                    load_spinor<float, float>(rout, SE.g, Vh, z);
                 }
             }
 #pragma unroll
@@ -334,7 +370,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
                 if (core) z[c] = {z[c].re + ar * r.x - ai * r.y, z[c].im + ar * r.y + ai * r.x};
                 sE[c * MAXNE + t] = make_float2(r.x - (ar * qv[c].re - ai * qv[c].im), r.y - (ar * qv[c].im + ai * qv[c].re));
             }
-            if (core) store_spinor<float, float>(rout, gE, Vh, z);
+            if (core) store_spinor<float, float>(rout, SE.g, Vh, z);
         }
     }
 }

@@ -340,7 +340,6 @@ WCL_D void store_spinor(void *base, uint32_t h, uint32_t Vh, const cplx<R> v[12]
     }
 }
 
-// Link U_mu at (parity p, half index h): 9 complex, row-major.
 template <typename R>
 WCL_D void su3_third_row(cplx<R> u[9])
 {
@@ -353,55 +352,89 @@ WCL_D void su3_third_row(cplx<R> u[9])
     u[8] = {c2.re, -c2.im};
 }
 
-template <typename S, typename R, bool NT = false>
-WCL_D void load_link(const void *base, int mu, int p, uint32_t h, uint32_t Vh, cplx<R> u[9])
+// A link as loaded (still encoded), so that a pipeline stage holds 12 (two
+// rows) or 18 reals and decodes at compute time.
+template <typename S> struct LinkRaw { float4 v[4]; float2 w; };
+template <> struct LinkRaw<double> { double2 v[9]; };
+template <> struct LinkRaw<__half> { uint4 v[2]; uint32_t w; };
+template <> struct LinkRaw<R12f> { float4 v[3]; };
+template <> struct LinkRaw<R12h> { uint4 v; uint2 w; };
+
+template <typename S, bool NT = false>
+WCL_D void load_link_raw(const void *base, int mu, int p, uint32_t h, uint32_t Vh, LinkRaw<S> &r)
 {
     const uint32_t mp = (uint32_t)(mu * 2 + p);
     if constexpr (std::is_same<S, R12f>::value) {
         // float4 [4][2][3][Vh]: rows 0 and 1
 #pragma unroll
-        for (uint32_t k = 0; k < 3; k++) {
-            const float4 f = ldx<NT, float4>(base, ((mp * 3 + k) * Vh + h) * 16u);
-            u[2 * k] = {(R)f.x, (R)f.y};
-            u[2 * k + 1] = {(R)f.z, (R)f.w};
+        for (uint32_t k = 0; k < 3; k++) r.v[k] = ldx<NT, float4>(base, ((mp * 3 + k) * Vh + h) * 16u);
+    } else if constexpr (std::is_same<S, R12h>::value) {
+        // 8 halves [4][2][Vh] (complex 0..3) + 4 halves [4][2][Vh] (complex 4, 5)
+        r.v = ldx<NT, uint4>(base, (mp * Vh + h) * 16u);
+        r.w = ldx<NT, uint2>(base, 8u * Vh * 16u + (mp * Vh + h) * 8u);
+    } else if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (uint32_t i = 0; i < 9; i++) r.v[i] = ldx<NT, double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
+    } else if constexpr (sizeof(S) == 4) {
+        // float4 [4][2][4][Vh] (complex 0..7) + float2 [4][2][Vh] (complex 8)
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) r.v[k] = ldx<NT, float4>(base, ((mp * 4 + k) * Vh + h) * 16u);
+        r.w = ldx<NT, float2>(base, 32u * Vh * 16u + (mp * Vh + h) * 8u);
+    } else {
+        // uint4 [4][2][2][Vh] (complex 0..7) + half2 [4][2][Vh] (complex 8)
+#pragma unroll
+        for (uint32_t k = 0; k < 2; k++) r.v[k] = ldx<NT, uint4>(base, ((mp * 2 + k) * Vh + h) * 16u);
+        r.w = ldx<NT, uint32_t>(base, 16u * Vh * 16u + (mp * Vh + h) * 4u);
+    }
+}
+
+template <typename S, typename R>
+WCL_D void expand_link(const LinkRaw<S> &r, cplx<R> u[9])
+{
+    if constexpr (std::is_same<S, R12f>::value) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            u[2 * k] = {(R)r.v[k].x, (R)r.v[k].y};
+            u[2 * k + 1] = {(R)r.v[k].z, (R)r.v[k].w};
         }
         su3_third_row(u);
     } else if constexpr (std::is_same<S, R12h>::value) {
-        // 8 halves [4][2][Vh] (complex 0..3) + 4 halves [4][2][Vh] (complex 4, 5)
-        const uint4 w = ldx<NT, uint4>(base, (mp * Vh + h) * 16u);
-        const uint2 v = ldx<NT, uint2>(base, 8u * Vh * 16u + (mp * Vh + h) * 8u);
-        const float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w), e = h2f2(v.x), f = h2f2(v.y);
+        const float2 a = h2f2(r.v.x), b = h2f2(r.v.y), c = h2f2(r.v.z), d = h2f2(r.v.w), e = h2f2(r.w.x),
+                     f = h2f2(r.w.y);
         u[0] = {(R)a.x, (R)a.y}; u[1] = {(R)b.x, (R)b.y}; u[2] = {(R)c.x, (R)c.y};
         u[3] = {(R)d.x, (R)d.y}; u[4] = {(R)e.x, (R)e.y}; u[5] = {(R)f.x, (R)f.y};
         su3_third_row(u);
     } else if constexpr (sizeof(S) == 8) {
 #pragma unroll
-        for (uint32_t i = 0; i < 9; i++) {
-            const double2 d = ldx<NT, double2>(base, ((mp * 9 + i) * Vh + h) * 16u);
-            u[i] = {(R)d.x, (R)d.y};
-        }
+        for (int i = 0; i < 9; i++) u[i] = {(R)r.v[i].x, (R)r.v[i].y};
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
-        for (uint32_t k = 0; k < 4; k++) {
-            const float4 f = ldx<NT, float4>(base, ((mp * 4 + k) * Vh + h) * 16u);
-            u[2 * k] = {(R)f.x, (R)f.y};
-            u[2 * k + 1] = {(R)f.z, (R)f.w};
+        for (int k = 0; k < 4; k++) {
+            u[2 * k] = {(R)r.v[k].x, (R)r.v[k].y};
+            u[2 * k + 1] = {(R)r.v[k].z, (R)r.v[k].w};
         }
-        const float2 f = ldx<NT, float2>(base, 32u * Vh * 16u + (mp * Vh + h) * 8u);
-        u[8] = {(R)f.x, (R)f.y};
+        u[8] = {(R)r.w.x, (R)r.w.y};
     } else {
 #pragma unroll
-        for (uint32_t k = 0; k < 2; k++) {
-            const uint4 w = ldx<NT, uint4>(base, ((mp * 2 + k) * Vh + h) * 16u);
-            float2 a = h2f2(w.x), b = h2f2(w.y), c = h2f2(w.z), d = h2f2(w.w);
+        for (int k = 0; k < 2; k++) {
+            const float2 a = h2f2(r.v[k].x), b = h2f2(r.v[k].y), c = h2f2(r.v[k].z), d = h2f2(r.v[k].w);
             u[4 * k + 0] = {(R)a.x, (R)a.y};
             u[4 * k + 1] = {(R)b.x, (R)b.y};
             u[4 * k + 2] = {(R)c.x, (R)c.y};
             u[4 * k + 3] = {(R)d.x, (R)d.y};
         }
-        const float2 f = h2f2(ldx<NT, uint32_t>(base, 16u * Vh * 16u + (mp * Vh + h) * 4u));
+        const float2 f = h2f2(r.w);
         u[8] = {(R)f.x, (R)f.y};
     }
+}
+
+// Link U_mu at (parity p, half index h): 9 complex, row-major.
+template <typename S, typename R, bool NT = false>
+WCL_D void load_link(const void *base, int mu, int p, uint32_t h, uint32_t Vh, cplx<R> u[9])
+{
+    LinkRaw<S> r;
+    load_link_raw<S, NT>(base, mu, p, h, Vh, r);
+    expand_link<S, R>(r, u);
 }
 
 template <typename S, typename R>
@@ -512,32 +545,48 @@ WCL_D void store_clover(void *base, int p, uint32_t h, uint32_t Vh, const double
 }
 
 // One chirality block (36 reals) of a clover site: half 0 = spins 0,1,
-// half 1 = spins 2,3.
-template <typename S, typename R>
-WCL_D void load_clover_half(const void *base, int p, uint32_t h, uint32_t Vh, int half, R c[36])
+// half 1 = spins 2,3.  ClovHalfRaw holds it as loaded (decoded later).
+template <typename S> struct ClovHalfRaw { float4 v[9]; };
+template <> struct ClovHalfRaw<double> { double2 v[18]; };
+template <> struct ClovHalfRaw<__half> { uint4 v[5]; };
+
+template <typename S>
+WCL_D void load_clover_half_raw(const void *base, int p, uint32_t h, uint32_t Vh, int half, ClovHalfRaw<S> &r)
 {
     static_assert(!std::is_empty<S>::value, "two-row link tags are link storage only");
     if constexpr (sizeof(S) == 8) {
 #pragma unroll
-        for (uint32_t k = 0; k < 18; k++) {
-            const double2 d = ldf<double2>(base, (((uint32_t)p * 36 + 18 * half + k) * Vh + h) * 16u);
-            c[2 * k] = (R)d.x;
-            c[2 * k + 1] = (R)d.y;
+        for (uint32_t k = 0; k < 18; k++) r.v[k] = ldf<double2>(base, (((uint32_t)p * 36 + 18 * half + k) * Vh + h) * 16u);
+    } else if constexpr (sizeof(S) == 4) {
+#pragma unroll
+        for (uint32_t k = 0; k < 9; k++) r.v[k] = ldf<float4>(base, (((uint32_t)p * 18 + 9 * half + k) * Vh + h) * 16u);
+    } else {
+        // 36 halves starting at half 36*half: uint4 words w0 .. w0+4 (8 halves each)
+        const uint32_t w0 = half ? 4u : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 5; k++) r.v[k] = ldf<uint4>(base, (((uint32_t)p * 9 + w0 + k) * Vh + h) * 16u);
+    }
+}
+
+template <typename S, typename R>
+WCL_D void expand_clover_half(const ClovHalfRaw<S> &r, int half, R c[36])
+{
+    if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            c[2 * k] = (R)r.v[k].x;
+            c[2 * k + 1] = (R)r.v[k].y;
         }
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
-        for (uint32_t k = 0; k < 9; k++) {
-            const float4 f = ldf<float4>(base, (((uint32_t)p * 18 + 9 * half + k) * Vh + h) * 16u);
-            c[4 * k] = f.x; c[4 * k + 1] = f.y; c[4 * k + 2] = f.z; c[4 * k + 3] = f.w;
+        for (int k = 0; k < 9; k++) {
+            c[4 * k] = r.v[k].x; c[4 * k + 1] = r.v[k].y; c[4 * k + 2] = r.v[k].z; c[4 * k + 3] = r.v[k].w;
         }
     } else {
-        // 36 halves starting at half 36*half: uint4 words w0 .. w0+4 (8 halves each)
         float t[40];
-        const uint32_t w0 = half ? 4u : 0u;
 #pragma unroll
-        for (uint32_t k = 0; k < 5; k++) {
-            const uint4 w = ldf<uint4>(base, (((uint32_t)p * 9 + w0 + k) * Vh + h) * 16u);
-            float2 a = h2f2(w.x), b = h2f2(w.y), cc = h2f2(w.z), d = h2f2(w.w);
+        for (int k = 0; k < 5; k++) {
+            float2 a = h2f2(r.v[k].x), b = h2f2(r.v[k].y), cc = h2f2(r.v[k].z), d = h2f2(r.v[k].w);
             t[8 * k + 0] = a.x; t[8 * k + 1] = a.y; t[8 * k + 2] = b.x; t[8 * k + 3] = b.y;
             t[8 * k + 4] = cc.x; t[8 * k + 5] = cc.y; t[8 * k + 6] = d.x; t[8 * k + 7] = d.y;
         }
@@ -545,6 +594,14 @@ WCL_D void load_clover_half(const void *base, int p, uint32_t h, uint32_t Vh, in
 #pragma unroll
         for (int k = 0; k < 36; k++) c[k] = (R)t[off + k];
     }
+}
+
+template <typename S, typename R>
+WCL_D void load_clover_half(const void *base, int p, uint32_t h, uint32_t Vh, int half, R c[36])
+{
+    ClovHalfRaw<S> r;
+    load_clover_half_raw<S>(base, p, h, Vh, half, r);
+    expand_clover_half<S, R>(r, half, c);
 }
 
 template <typename R>
