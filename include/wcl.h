@@ -100,18 +100,30 @@ int wcl_apply(wcl_ctx *ctx, const double *in_dev, double *out_dev, int nrhs, int
  *   WCL_OP_SCHUR      out_e = Dhat in_e, out_o = 0, Dhat = 1 - k^2 T_ee^-1 H_eo T_oo^-1 H_oe
  *   WCL_OP_SCHUR_RHS  out_e = T_ee^-1 (in_e + k H_eo T_oo^-1 in_o), out_o = 0
  *   WCL_OP_RAS        out_e = M in_e, out_o = 0   (one RAS application; prec 32 or 16,
- *                     overlap and iterations from the last wcl_set_ras, default 1 and 4)
+ *                     overlap, iterations and block solver from the last wcl_set_ras,
+ *                     default 1, 4 and minimal residual)
  *   WCL_OP_D / WCL_OP_DDAG as wcl_apply.                                   */
 enum { WCL_OP_HOP = 0, WCL_OP_CLOVER = 1, WCL_OP_CLOVER_INV = 2, WCL_OP_SCHUR = 3,
        WCL_OP_SCHUR_RHS = 4, WCL_OP_RAS = 5, WCL_OP_D = 6, WCL_OP_DDAG = 7 };
 int wcl_apply_op(wcl_ctx *ctx, int op, const double *in_dev, double *out_dev, int nrhs, int prec);
-int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters);
+/* Schwarz settings of WCL_OP_RAS (a solve sets them from its options):
+ * overlap (extension of the cores on every side), iters (block steps) and
+ * the block solver: WCL_RAS_MR, minimal residual from zero (the default),
+ * or WCL_RAS_JACOBI, the linear alternative z <- z + (r_B - Dhat_B z)
+ * (the paper leaves the block solver open, Sec. 2).  WCL_EINVAL when the
+ * extended block does not fit the lattice or one workgroup. */
+enum { WCL_RAS_MR = 0, WCL_RAS_JACOBI = 1 };
+int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters, int solver);
 
 /* Solver options. */
-enum { WCL_OUTER_FBICGSTAB = 0, WCL_OUTER_DC = 1, WCL_OUTER_PLAIN64 = 2 };
+/* FBICGSTAB: FP64 flexible BiCGStab on the even/odd system, preconditioned
+ * by the inner single-precision solve (Sec. 2); DC: defect correction with the
+ * same inner solve; PLAIN64: unpreconditioned FP64 BiCGStab on the full D;
+ * PLAIN64_EO: unpreconditioned FP64 BiCGStab on the even/odd system. */
+enum { WCL_OUTER_FBICGSTAB = 0, WCL_OUTER_DC = 1, WCL_OUTER_PLAIN64 = 2, WCL_OUTER_PLAIN64_EO = 3 };
 typedef struct {
     double tol;          /* stop when ||b - D x|| / ||b|| <= tol (true FP64 residual) */
-    int max_outer;       /* outer iterations (PLAIN64: BiCGStab iterations)          */
+    int max_outer;       /* outer iterations (PLAIN64*: BiCGStab iterations)         */
     int max_inner;       /* inner iterations per preconditioner call                 */
     double inner_tol;    /* inner relative residual                                  */
     int outer;           /* WCL_OUTER_*                                              */
@@ -122,6 +134,7 @@ typedef struct {
     int use_graph;       /* replay the inner iteration as a captured hipGraph        */
     int check_every;     /* inner iterations between host convergence checks         */
     int adjoint;         /* 1: solve D^dag x = b instead, as x = g5 D^-1 (g5 b)      */
+    int ras_solver;      /* WCL_RAS_MR or WCL_RAS_JACOBI (block solver of the RAS)   */
 } wcl_solve_opts;
 
 typedef struct {

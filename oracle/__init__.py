@@ -62,7 +62,7 @@ def _load():
     lib.wco_reconstruct.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
     for name in ("wco_field_strength", "wco_clover_matrix", "wco_clover_inv_matrix"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, _dp]
-    lib.wco_ras.argtypes = [ctypes.c_void_p, _ip, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.wco_ras.argtypes = [ctypes.c_void_p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.wco_ras.restype = ctypes.c_int
     for name in ("wco_bicgstab_full", "wco_bicgstab_eo"):
         f = getattr(lib, name)
@@ -194,10 +194,11 @@ class Oracle:
         self._lib.wco_reconstruct(self._h, _p(bb), _p(xx), _p(out))
         return out
 
-    def ras(self, v, block=(4, 4, 4, 4), overlap: int = 1, iters: int = 4):
+    def ras(self, v, block=(4, 4, 4, 4), overlap: int = 1, iters: int = 4, solver: int = 0):
+        """One RAS application (solver 0: minimal residual, 1: block Jacobi)."""
         a = self._spinor(v)
         out = np.empty_like(a)
-        rc = self._lib.wco_ras(self._h, _ivec(block), int(overlap), int(iters), _p(a), _p(out))
+        rc = self._lib.wco_ras(self._h, _ivec(block), int(overlap), int(iters), int(solver), _p(a), _p(out))
         if rc != 0:
             raise ValueError("oracle RAS: block shape does not fit the lattice")
         return out

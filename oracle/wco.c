@@ -759,9 +759,10 @@ static void block_schur(const wco_ctx *c, const blockmap *B, const cplx *x, cplx
     block_mask(c, B, out, 0);
 }
 
-int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, const double *in,
-            double *out)
+int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
+            const double *in, double *out)
 {
+    if (solver != 0 && solver != 1) return -1;
     for (int mu = 0; mu < 4; mu++) {
         if (block[mu] < 2 || (block[mu] & 1) || c->L[mu] % block[mu]) return -1;
         if (c->L[mu] < block[mu] + 2 * overlap || overlap < 0) return -1;
@@ -797,12 +798,16 @@ int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, const 
         for (long l = 0; l < B.Ne; l++)
             for (int i = 0; i < 12; i++) r[l * 12 + i] = vin[B.g[l] * 12 + i];
         block_mask(c, &B, r, 0);
-        /* minimal residual from z = 0 */
+        /* from z = 0, r = r_B: minimal residual (alpha = <q, r> / <q, q>) or
+         * block Jacobi (alpha = 1), with q = Dhat_B r */
         for (int k = 0; k < iters; k++) {
             block_schur(c, &B, r, q, t1, t2);
-            const double qq = creal(vdot(N, q, q));
-            if (qq == 0.0) break;
-            const cplx alpha = vdot(N, q, r) / qq;
+            cplx alpha = 1.0;
+            if (solver == 0) {
+                const double qq = creal(vdot(N, q, q));
+                if (qq == 0.0) break;
+                alpha = vdot(N, q, r) / qq;
+            }
             for (long i = 0; i < N; i++) { z[i] += alpha * r[i]; r[i] -= alpha * q[i]; }
         }
         /* restriction: keep the even core sites */
@@ -831,7 +836,7 @@ typedef struct {
 
 static void apply_precond(const wco_ctx *c, const precond *P, const cplx *in, cplx *out)
 {
-    if (P->use_ras) wco_ras(c, P->block, P->overlap, P->iters, (const double *)in, (double *)out);
+    if (P->use_ras) wco_ras(c, P->block, P->overlap, P->iters, 0, (const double *)in, (double *)out);
     else memcpy(out, in, sizeof(cplx) * 12 * c->V);
 }
 

@@ -58,8 +58,10 @@ void wco_schur(const wco_ctx *c, const double *xe, double *out);
 void wco_schur_rhs(const wco_ctx *c, const double *b, double *bhat);
 void wco_reconstruct(const wco_ctx *c, const double *b, const double *xe, double *x);
 
-/* Overlapped restricted additive Schwarz (one application) on even vectors. */
-int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters,
+/* Overlapped restricted additive Schwarz (one application) on even vectors.
+ * solver 0: minimal residual steps from z = 0; solver 1: the linear block
+ * Jacobi (Richardson) steps z <- z + (r_B - Dhat_B z) from z = 0. */
+int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
             const double *in, double *out);
 
 /* Solvers; return 0 on convergence, 1 if max iterations hit, 2 on breakdown.

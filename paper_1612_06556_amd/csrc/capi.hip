@@ -62,7 +62,7 @@ struct wcl_ctx {
     int *info = nullptr;
     double kappa = 0, csw = 0;
     bool have_gauge = false, have_params = false;
-    int ras_overlap = 1, ras_iters = 4;
+    int ras_overlap = 1, ras_iters = 4, ras_solver = WCL_RAS_MR;
     std::vector<Buf> ws;        // workspace, indexed by slot
     double *partials = nullptr; // [cap][6][RED_BLOCKS]
     Scalars *sc = nullptr;      // [3][cap]: outer, inner, final/scratch scalars per right-hand side
@@ -572,16 +572,18 @@ int wcl_set_params(wcl_ctx *c, double kappa, double csw)
     return WCL_OK;
 }
 
-int wcl_set_ras(wcl_ctx *c, int overlap, int iters)
+int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver)
 {
     if (!c) return fail(WCL_EINVAL, "null context");
     if (overlap < 0 || iters < 1) return fail(WCL_EINVAL, "overlap >= 0 and iters >= 1 required");
+    if (solver != WCL_RAS_MR && solver != WCL_RAS_JACOBI) return fail(WCL_EINVAL, "unknown RAS block solver");
     for (int mu = 0; mu < 4; mu++)
         if (overlap > c->g.B[mu] || c->g.L[mu] < c->g.B[mu] + 2 * overlap)
             return fail(WCL_EINVAL, "RAS extended block does not fit the lattice");
     if (ras_threads(c->g, overlap) > 1024) return fail(WCL_EINVAL, "RAS extended block too large for one workgroup");
     c->ras_overlap = overlap;
     c->ras_iters = iters;
+    c->ras_solver = solver;
     return WCL_OK;
 }
 
@@ -644,6 +646,7 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.g = &c->g;
             R.overlap = c->ras_overlap;
             R.iters = c->ras_iters;
+            R.jacobi = c->ras_solver == WCL_RAS_JACOBI;
             R.link_prec = eff_lprec(c, lp);
             R.in = par(a, sp, Vh, 0);
             R.out = par(b, sp, Vh, 0);
@@ -688,6 +691,7 @@ void wcl_default_opts(wcl_solve_opts *o)
     o->use_ras = 1;
     o->ras_overlap = 1;
     o->ras_iters = 4;
+    o->ras_solver = WCL_RAS_MR;
     o->inner_prec = 32;
     o->use_graph = 0;
     o->check_every = 8;
@@ -754,6 +758,7 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         R.g = &c->g;
         R.overlap = c->ras_overlap;
         R.iters = c->ras_iters;
+        R.jacobi = c->ras_solver == WCL_RAS_JACOBI;
         R.link_prec = eff_lprec(c, lp);
         R.links = links_for(c, R.link_prec);
         R.clov_inv = clovinv_for(c, lp);
@@ -907,28 +912,30 @@ int write_final(wcl_ctx *c, const std::vector<int> &final_)
 
 // Generic BiCGStab driver for n right-hand sides in FP64 (right
 // preconditioned by K when given):
-//   PLAIN  : A = full D on full fields, no K, x = w.x, rhs = w.b
-//   FLEX   : A = Dhat on even vectors, K = inner solve, x = w.xe, rhs = w.bh
+//   PLAIN    : A = full D on full fields, no K, x = w.x, rhs = w.b
+//   PLAIN_EO : A = Dhat on even vectors, no K, x = w.xe, rhs = w.bh
+//   FLEX     : A = Dhat on even vectors, K = inner solve, x = w.xe, rhs = w.bh
 // Stops a right-hand side when its true residual of the full system is
 // <= tol; a right-hand side whose recursive residual reached the threshold
 // (or broke down) without a true residual <= tol gets its residual replaced
 // by the true one and its recurrence restarted.
 struct Driver {
-    bool flex;
+    bool eo;        // A = Dhat on even vectors (else the full D)
+    bool flex;      // right preconditioned by the inner solve
     size_t m;       // complex numbers per right-hand side
     void *x, *bvec;
 };
 
 int apply_A(wcl_ctx *c, const Driver &d, SolveWs &w, const void *in, void *out, const Scalars *sc)
 {
-    if (d.flex) return schur(c, P64, P64, in, out, w.o, sc, w.n);
+    if (d.eo) return schur(c, P64, P64, in, out, w.o, sc, w.n);
     return full_D(c, P64, P64, in, out, 0, sc, w.n);
 }
 
 // true residuals; for FLEX the full solution is reconstructed first
 int check_true(wcl_ctx *c, const Driver &d, SolveWs &w, const std::vector<double> &bnorm2, std::vector<double> &rel)
 {
-    if (d.flex) {
+    if (d.eo) {
         HIPCHK(launch_zero(P64, w.n * 24 * (size_t)c->Vh, w.x, c->st));
         // copy x_e into the even halves of the full fields
         for (int k = 0; k < w.n; k++)
@@ -1076,7 +1083,7 @@ int outer_dc(wcl_ctx *c, const wcl_solve_opts &o, const InnerCfg &cfg, SolveWs &
     HIPCHK(launch_copy(P64, n * m, w.bh, w.r, c->st));
     HIPCHK(launch_zero(P64, n * m, w.xe, c->st));
     std::vector<int> it(n, 0);
-    Driver d{true, m, w.xe, w.bh};
+    Driver d{true, true, m, w.xe, w.bh};
     for (int outer = 0; outer < o.max_outer; outer++) {
         bool any_active = false;
         for (int k = 0; k < n; k++) any_active = any_active || !final_[k];
@@ -1124,18 +1131,20 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     else wcl_default_opts(&o);
     if (!(o.tol > 0) || o.max_outer < 1 || o.max_inner < 1 || !(o.inner_tol > 0))
         return fail(WCL_EINVAL, "tol, inner_tol > 0 and iteration limits >= 1 required");
-    if (o.outer < 0 || o.outer > WCL_OUTER_PLAIN64) return fail(WCL_EINVAL, "unknown outer solver");
+    if (o.outer < 0 || o.outer > WCL_OUTER_PLAIN64_EO) return fail(WCL_EINVAL, "unknown outer solver");
     if (o.inner_prec != 32 && o.inner_prec != 16) return fail(WCL_EINVAL, "inner_prec must be 32 or 16");
     if (o.check_every < 1) o.check_every = 8;
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
-    if (o.use_ras && !plain) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters));
+    const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
+    const bool inner = !plain && !plain_eo;
+    if (o.use_ras && inner) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver));
     const int n = nrhs;
     CHK(ensure_batch(c, n));
     SolveWs w;
-    CHK(get_ws(c, w, !plain, plain, n));
+    CHK(get_ws(c, w, inner, plain, n));
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;
-    if (o.use_graph && !plain) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    if (o.use_graph && inner) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     struct GraphGuard {
         hipGraphExec_t *e;
         hipStream_t *s;
@@ -1146,7 +1155,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         }
     } guard{&graph_exec, &cap_stream};
     InnerCfg cfg{o.inner_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every,
-                 o.use_graph != 0 && !plain, &graph_exec, cap_stream};
+                 o.use_graph != 0 && inner, &graph_exec, cap_stream};
     // the inner stopping threshold is fixed for the whole solve
     for (int k = 0; k < n; k++) {
         HI(c)[k] = Scalars{};
@@ -1169,12 +1178,15 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         else if (bnorm2[k] == 0.0) { final_[k] = 1; info[k].status = WCL_OK; }
     }
     if (plain) {
-        Driver d{false, 24 * (size_t)c->Vh, w.x, w.b};
+        Driver d{false, false, 24 * (size_t)c->Vh, w.x, w.b};
         CHK(bicgstab_driver(c, d, o, nullptr, w, bnorm2, final_, info));
     } else {
         CHK(schur_rhs64(c, w.b, w.bh, w.o, w.s, n));
-        if (o.outer == WCL_OUTER_FBICGSTAB) {
-            Driver d{true, 12 * (size_t)c->Vh, w.xe, w.bh};
+        if (plain_eo) {
+            Driver d{true, false, 12 * (size_t)c->Vh, w.xe, w.bh};
+            CHK(bicgstab_driver(c, d, o, nullptr, w, bnorm2, final_, info));
+        } else if (o.outer == WCL_OUTER_FBICGSTAB) {
+            Driver d{true, true, 12 * (size_t)c->Vh, w.xe, w.bh};
             CHK(bicgstab_driver(c, d, o, &cfg, w, bnorm2, final_, info));
         } else {
             CHK(outer_dc(c, o, cfg, w, bnorm2, final_, info));

@@ -30,6 +30,7 @@ struct RasArgs {
     const Scalars *sc;
     int nrhs;
     size_t stride;   // bytes between right-hand sides
+    int jacobi;      // block steps with alpha = 1 (no reductions)
 };
 
 // global (tile coordinate, in-tile coordinate) of extended-block coordinate a
@@ -341,18 +342,25 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             for (int c = 0; c < 12; c++) {
                 const float2 r = sE[c * MAXNE + t];
                 qv[c] = {fmaf(-a.kappa2, w[c].re, r.x), fmaf(-a.kappa2, w[c].im, r.y)};
-                qr += qv[c].re * r.x + qv[c].im * r.y;
-                qi += qv[c].re * r.y - qv[c].im * r.x;
-                qq += qv[c].re * qv[c].re + qv[c].im * qv[c].im;
+                if (!a.jacobi) {
+                    qr += qv[c].re * r.x + qv[c].im * r.y;
+                    qi += qv[c].re * r.y - qv[c].im * r.x;
+                    qq += qv[c].re * qv[c].re + qv[c].im * qv[c].im;
+                }
             }
             dots[0] = qr; dots[1] = qi; dots[2] = qq;
         } else {
 #pragma unroll
             for (int c = 0; c < 12; c++) qv[c] = {0.f, 0.f};
         }
-        block_allreduce<3>(dots, red);
-        if (dots[2] == 0.0) break;
-        const float ar = (float)(dots[0] / dots[2]), ai = (float)(dots[1] / dots[2]);
+        float ar = 1.f, ai = 0.f;
+        if (!a.jacobi) {
+            // minimal residual: alpha = <q, r> / <q, q> over the block
+            block_allreduce<3>(dots, red);
+            if (dots[2] == 0.0) break;
+            ar = (float)(dots[0] / dots[2]);
+            ai = (float)(dots[1] / dots[2]);
+        }
         if (active) {
             // z += alpha r (kept only where it is written: the core), r -= alpha q
             cplx<float> z[12];
@@ -406,6 +414,7 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.sc = L.sc;
     a.nrhs = L.nrhs;
     a.stride = L.stride;
+    a.jacobi = L.jacobi ? 1 : 0;
     const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     const int threads = ras_threads(g, L.overlap);
     if (threads > 1024) return hipErrorInvalidValue;
@@ -449,8 +458,8 @@ void ras_work(const RasLaunch &L, double *bytes, double *flops)
     for (int mu = 0; mu < 4; mu++) hops += 2.0 * (e[mu] - 1) * ext / e[mu];
     const double ne = ext / 2.0;
     // per iteration: hops, clover on every site, q = r - k^2 w (48 per even site),
-    // two dot products (96) and the z, r updates (96)
-    const double per_iter = hops * 168.0 + ext * 504.0 + ne * (48.0 + 96.0 + 96.0);
+    // two dot products (96, minimal residual only) and the z, r updates (96)
+    const double per_iter = hops * 168.0 + ext * 504.0 + ne * (48.0 + (L.jacobi ? 0.0 : 96.0) + 96.0);
     const double nblk = (double)g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     *flops = per_iter * L.iters * nblk * nr;
 }

@@ -152,6 +152,7 @@ struct RasLaunch {
     const Scalars *sc;   // may be null; per right-hand side, skips when done
     int nrhs;            // right-hand sides, fields `stride` bytes apart
     size_t stride;
+    bool jacobi;         // block solver: false = minimal residual, true = z += r, r -= Dhat_B r
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libwcl.so")
 WCL_OK, WCL_EINVAL, WCL_ENOMEM, WCL_EHIP, WCL_ENOCONV, WCL_EBREAKDOWN, WCL_ENAN, WCL_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 OP_HOP, OP_CLOVER, OP_CLOVER_INV, OP_SCHUR, OP_SCHUR_RHS, OP_RAS, OP_D, OP_DDAG = range(8)
-OUTER_FBICGSTAB, OUTER_DC, OUTER_PLAIN64 = 0, 1, 2
+OUTER_FBICGSTAB, OUTER_DC, OUTER_PLAIN64, OUTER_PLAIN64_EO = 0, 1, 2, 3
+RAS_MR, RAS_JACOBI = 0, 1
 
 
 class WclError(RuntimeError):
@@ -34,7 +35,8 @@ class wcl_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("outer", ctypes.c_int), ("use_ras", ctypes.c_int),
                 ("ras_overlap", ctypes.c_int), ("ras_iters", ctypes.c_int), ("inner_prec", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int),
+                ("ras_solver", ctypes.c_int)]
 
 
 class wcl_solve_info(ctypes.Structure):
@@ -71,7 +73,7 @@ def load():
     lib.wcl_set_stream.argtypes = [_vp, _vp]
     lib.wcl_set_gauge.argtypes = [_vp, _vp]
     lib.wcl_set_params.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
-    lib.wcl_set_ras.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    lib.wcl_set_ras.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply_op.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int]
     lib.wcl_default_opts.argtypes = [ctypes.POINTER(wcl_solve_opts)]
@@ -126,8 +128,8 @@ def wcl_set_params(h, kappa, csw):
     _check(load().wcl_set_params(h, float(kappa), float(csw)))
 
 
-def wcl_set_ras(h, overlap, iters):
-    _check(load().wcl_set_ras(h, int(overlap), int(iters)))
+def wcl_set_ras(h, overlap, iters, solver=0):
+    _check(load().wcl_set_ras(h, int(overlap), int(iters), int(solver)))
 
 
 def wcl_apply(h, in_ptr, out_ptr, nrhs, dagger, prec):
@@ -259,8 +261,9 @@ class Lattice:
         wcl_apply_op(self.h, op, psi.data_ptr(), out.data_ptr(), nrhs, prec)
         return out
 
-    def set_ras(self, overlap=1, iters=4):
-        wcl_set_ras(self.h, overlap, iters)
+    def set_ras(self, overlap=1, iters=4, solver=0):
+        """RAS overlap, block steps and block solver (RAS_MR or RAS_JACOBI)."""
+        wcl_set_ras(self.h, overlap, iters, solver)
 
     def solve(self, b, raise_on_error=True, **kw):
         b, nrhs = self._spinors(b)

@@ -85,6 +85,25 @@ def test_ras_block_solve(case, prec):
     assert e <= (1e-5 if prec == 32 else 3e-3)
 
 
+@pytest.mark.parametrize("overlap,solver,iters", [(1, 1, 4), (0, 0, 4), (0, 1, 3)])
+def test_ras_variants(overlap, solver, iters):
+    """Block Jacobi steps and overlap 0 against the oracle's RAS (FP32, 1e-5)."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    psi = synth.gaussian_spinor(dims, 15)
+    psi[~even_mask(dims)] = 0
+    lat.set_ras(overlap, iters, solver)
+    try:
+        out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=32))
+    finally:
+        lat.set_ras(1, 4, 0)
+    ref = orc.ras(psi, (4, 4, 4, 4), overlap, iters, solver)
+    e = rel(out, ref)
+    print(f"ras overlap={overlap} solver={solver} rel={e:.3e}", flush=True)
+    assert e <= 1e-5
+
+
 def test_ras_small_cores():
     """2^4 cores with overlap 1 on a 4x4x4x8 lattice (extended block = 4^4)."""
     from paper_1612_06556_amd import wcl

@@ -109,11 +109,12 @@ def test_neumann_series_small_kappa():
     assert rel(o.clover(b), b - csw * kappa * o.clover_C(b)) < 1e-15
 
 
-def _ras_bruteforce(o, dims, U, v, block, overlap, iters):
+def _ras_bruteforce(o, dims, U, v, block, overlap, iters, solver=0):
     """RAS from the pinned global operator: per block, a copy of the oracle on a
     gauge field that keeps only the links between locally adjacent sites of the
     extended block (all other links zero), so its hop is the Dirichlet block
-    hop; minimal residual in numpy; keep the even core sites."""
+    hop; minimal residual (solver 0) or block Jacobi steps with alpha = 1
+    (solver 1) in numpy; keep the even core sites."""
     V = len(v)
     X = coords(dims)
     even = parity(dims) == 0
@@ -151,7 +152,7 @@ def _ras_bruteforce(o, dims, U, v, block, overlap, iters):
         z = np.zeros_like(v)
         for _ in range(iters):
             q = dhat(r)
-            alpha = np.vdot(q, r) / np.vdot(q, q).real
+            alpha = np.vdot(q, r) / np.vdot(q, q).real if solver == 0 else 1.0
             z = z + alpha * r
             r = r - alpha * q
         core = inside & even
@@ -161,18 +162,39 @@ def _ras_bruteforce(o, dims, U, v, block, overlap, iters):
     return out
 
 
+@pytest.mark.parametrize("solver", [0, 1])
 @pytest.mark.parametrize("dims,block,overlap", [((4, 4, 4, 4), (2, 2, 2, 2), 1),
                                                 ((8, 4, 4, 4), (4, 2, 2, 2), 1),
                                                 ((4, 4, 4, 8), (2, 2, 2, 4), 0)])
-def test_ras_bruteforce(dims, block, overlap):
+def test_ras_bruteforce(dims, block, overlap, solver):
     U = synth.su3_field(dims, 81)
     o = oracle.Oracle(dims, -1, 0.125, 1.0, U)
     v = synth.gaussian_spinor(dims, 82)
     v[parity(dims) == 1] = 0
-    got = o.ras(v, block, overlap, 4)
-    ref = _ras_bruteforce(o, dims, U, v, block, overlap, 4)
+    got = o.ras(v, block, overlap, 4, solver)
+    ref = _ras_bruteforce(o, dims, U, v, block, overlap, 4, solver)
     assert rel(got, ref) < 1e-13
     assert np.abs(got[parity(dims) == 1]).max() == 0.0
+
+
+def test_ras_jacobi_one_and_two_steps():
+    """Block Jacobi from z = 0: one step gives z = r_B, two give 2 r_B - Dhat_B r_B;
+    on a vector supported deep inside one core, Dhat_B acts as the global Dhat
+    (hops reaching the cut need two sites), so the core output is
+    2 v - Dhat v there."""
+    dims = (8, 8, 8, 8)
+    o = oracle.Oracle(dims, -1, 0.124, 1.0, synth.su3_field(dims, 83))
+    X = coords(dims)
+    v = synth.gaussian_spinor(dims, 84)
+    deep = np.all((X % 4 >= 1) & (X % 4 <= 2), axis=1) & np.all(X < 4, axis=1)
+    v[~deep | (parity(dims) == 1)] = 0
+    assert np.abs(v).max() > 0
+    m1 = o.ras(v, (4, 4, 4, 4), 1, 1, 1)
+    assert rel(m1, v) < 1e-15
+    m2 = o.ras(v, (4, 4, 4, 4), 1, 2, 1)
+    core0 = np.all(X < 4, axis=1) & (parity(dims) == 0)
+    ref = 2 * v - o.schur(v)
+    assert rel(m2[core0], ref[core0]) < 1e-13
 
 
 def test_ras_rejects_bad_blocks():
