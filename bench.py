@@ -15,7 +15,7 @@ fused axpy, the RAS block work) over the timed wall time.  The roofline
 object describes the kernel class that takes the most GPU time, measured
 with HIP events on the library's stream inside the timed steps.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--sweep]
 """
 import argparse
 import json
@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the ablation solves")
+    ap.add_argument("--sweep", action="store_true",
+                    help="add the solver sweeps: lattice size, Schwarz variants, inner tolerance, 12-RHS batch")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of known size "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -168,6 +170,115 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     return out
 
 
+def _timed_solve(lat, b, torch, runs=3, **kw):
+    """Median wall time of `runs` solves after one warm-up, with the profiled
+    GFlop/s of the last one."""
+    from paper_1612_06556_amd import wcl
+    lat.solve(b, **kw)
+    torch.cuda.synchronize()
+    ts = []
+    for i in range(runs):
+        if i == runs - 1:
+            wcl.wcl_profile(lat.h, 1)
+        t1 = time.perf_counter()
+        _, info, _ = lat.solve(b, **kw)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    fl = sum(wcl.wcl_profile_read(lat.h, k)["flops"] for k in (wcl.K_HOP, wcl.K_RAS, wcl.K_CLOVER))
+    wcl.wcl_profile(lat.h, 0)
+    info = info if isinstance(info, dict) else info[0]
+    return {"ms": round(float(np.median(ts)) * 1e3, 2), "GFlop/s": round(fl / ts[-1] / 1e9, 1),
+            "outer": info["outer_iters"], "inner": info["inner_iters_total"], "true_relres": info["true_relres"]}
+
+
+def sweep(opts, torch, synth, wcl):
+    """Solver performance against lattice size, Schwarz and inner-tolerance
+    variants at 24^3x32, and the 12-point-source batch at 32^3x64."""
+    out = {}
+    sizes = {}
+    for dims, kappa, seed in (((8, 8, 8, 8), 0.12, 1001), ((16, 16, 16, 32), 0.125, 1002),
+                              ((24, 24, 24, 32), 0.126, 1003), ((32, 32, 32, 64), 0.126, 1004)):
+        U = torch.from_numpy(synth.su3_field(dims, seed)).cuda()
+        b = torch.from_numpy(synth.gaussian_spinor(dims, seed + 1000)).cuda()
+        lat = wcl.Lattice(dims, -1)
+        lat.set_compression(1)
+        lat.set_gauge(U)
+        lat.set_params(kappa, CSW)
+        wcl.wcl_autotune_hop(lat.h, 32, 2)
+        vh = int(np.prod(dims)) // 2
+        ms = _median_ms(lambda: lat.bench_hop(32, 100, 4))
+        row = {"kappa": kappa, "hop_fp32_r12_cold": _rate(ms, vh, 1320, 8 * 48 + 192)}
+        for name, kw in (("mixed_ras_fp32", dict(opts, outer=wcl.OUTER_FBICGSTAB)),
+                         ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
+                         ("plain_fp64_eo", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64_EO, max_outer=20000)),
+                         ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):
+            row[name] = _timed_solve(lat, b, torch, **kw)
+        sizes["x".join(map(str, dims))] = row
+        print(f"sweep: lattice {dims} done", file=sys.stderr, flush=True)
+        lat.close()
+        del U, b
+    out["lattice_size"] = sizes
+
+    dims = (24, 24, 24, 32)
+    U = torch.from_numpy(synth.su3_field(dims, 1003)).cuda()
+    b = torch.from_numpy(synth.gaussian_spinor(dims, 2003)).cuda()
+    lat = wcl.Lattice(dims, -1)
+    lat.set_compression(1)
+    lat.set_gauge(U)
+    lat.set_params(KAPPA, CSW)
+    wcl.wcl_autotune_hop(lat.h, 32, 4)
+    schwarz = {}
+    for name, kw in (("mr_overlap1_iters4", {}),
+                     ("mr_overlap1_iters2", dict(ras_iters=2)),
+                     ("mr_overlap1_iters8", dict(ras_iters=8)),
+                     ("mr_overlap0_iters4", dict(ras_overlap=0)),
+                     ("jacobi_overlap1_iters4", dict(ras_solver=wcl.RAS_JACOBI)),
+                     ("jacobi_overlap0_iters4", dict(ras_solver=wcl.RAS_JACOBI, ras_overlap=0)),
+                     ("defect_correction_mr", dict(outer=wcl.OUTER_DC)),
+                     ("no_ras", dict(use_ras=0))):
+        schwarz[name] = _timed_solve(lat, b, torch, **dict(opts, **kw))
+    out["schwarz_24x24x24x32"] = schwarz
+    print("sweep: Schwarz variants done", file=sys.stderr, flush=True)
+    stol = {}
+    for tol in (1e-1, 1e-2, 1e-3, 1e-4):
+        stol[f"{tol:g}"] = {"ras_fp32": _timed_solve(lat, b, torch, **dict(opts, inner_tol=tol)),
+                           "noras_fp16": _timed_solve(lat, b, torch, **dict(opts, inner_tol=tol, use_ras=0,
+                                                                              inner_prec=16))}
+    out["inner_tol_24x24x24x32"] = stol
+    print("sweep: inner tolerance done", file=sys.stderr, flush=True)
+    lat.close()
+    del U, b
+
+    # 12 point sources (spin x colour at the origin) at 32^3x64
+    dims = (32, 32, 32, 64)
+    U = torch.from_numpy(synth.su3_field(dims, 1004)).cuda()
+    b = torch.from_numpy(synth.point_sources(dims)).cuda()
+    lat = wcl.Lattice(dims, -1)
+    lat.set_compression(1)
+    lat.set_gauge(U)
+    lat.set_params(KAPPA, CSW)
+    wcl.wcl_autotune_hop(lat.h, 16, 2)
+    batch = {}
+    for name, kw in (("ras_fp16", dict(opts, inner_prec=16)), ("noras_fp16", dict(opts, use_ras=0, inner_prec=16))):
+        r12 = _timed_solve(lat, b, torch, runs=1, **kw)
+        t1 = time.perf_counter()
+        for k in range(12):
+            lat.solve(b[k], **kw)
+        torch.cuda.synchronize()
+        seq = (time.perf_counter() - t1) * 1e3
+        batch[name] = {"batched_12_ms": r12["ms"], "sequential_12_ms": round(seq, 1),
+                       "per_propagator_ms": round(r12["ms"] / 12, 2), "GFlop/s": r12["GFlop/s"],
+                       "inner": r12["inner"]}
+    t1 = time.perf_counter()
+    for k in range(2):
+        lat.solve(b[k], tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000)
+    torch.cuda.synchronize()
+    batch["plain_fp64_per_rhs_ms"] = round((time.perf_counter() - t1) * 1e3 / 2, 1)
+    out["batch12_32x32x32x64"] = batch
+    lat.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,6 +384,8 @@ def main():
     if not args.no_extras:
         out.update(extras(lat, U, gb, opts, Vh, torch, synth, wcl))
 
+    if args.sweep:
+        out["sweep"] = sweep(opts, torch, synth, wcl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U, b)
     print(json.dumps(out), flush=True)

@@ -30,7 +30,6 @@ struct RasArgs {
     const Scalars *sc;
     int nrhs;
     size_t stride;   // bytes between right-hand sides
-    int jacobi;      // block steps with alpha = 1 (no reductions)
 };
 
 // global (tile coordinate, in-tile coordinate) of extended-block coordinate a
@@ -210,7 +209,10 @@ WCL_D void block_allreduce(double v[NV], double *red)
     for (int k = 0; k < NV; k++) v[k] = red[NV * 16 + k];
 }
 
-template <typename SL, int MAXNE>
+// JAC: block Jacobi steps (alpha = 1, no reductions) instead of minimal
+// residual; a template parameter so that the minimal-residual kernel keeps
+// its registers.
+template <typename SL, int MAXNE, bool JAC>
 __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 {
     // workgroup id = tile * nrhs + rhs (the right-hand sides of one tile share
@@ -342,7 +344,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             for (int c = 0; c < 12; c++) {
                 const float2 r = sE[c * MAXNE + t];
                 qv[c] = {fmaf(-a.kappa2, w[c].re, r.x), fmaf(-a.kappa2, w[c].im, r.y)};
-                if (!a.jacobi) {
+                if constexpr (!JAC) {
                     qr += qv[c].re * r.x + qv[c].im * r.y;
                     qi += qv[c].re * r.y - qv[c].im * r.x;
                     qq += qv[c].re * qv[c].re + qv[c].im * qv[c].im;
@@ -354,7 +356,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             for (int c = 0; c < 12; c++) qv[c] = {0.f, 0.f};
         }
         float ar = 1.f, ai = 0.f;
-        if (!a.jacobi) {
+        if constexpr (!JAC) {
             // minimal residual: alpha = <q, r> / <q, q> over the block
             block_allreduce<3>(dots, red);
             if (dots[2] == 0.0) break;
@@ -391,6 +393,19 @@ int ras_threads(const Geom &g, int overlap)
     return ((n + 63) / 64) * 64;
 }
 
+template <int MAXNE, bool JAC>
+hipError_t ras_dispatch(const RasLaunch &L, const RasArgs &a, dim3 grid, dim3 block, hipStream_t st)
+{
+    switch (L.link_prec) {
+        case P32: k_ras<float, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
+        case P16: k_ras<__half, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
+        case P32C: k_ras<R12f, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
+        case P16C: k_ras<R12h, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
 {
     const Geom &g = *L.g;
@@ -414,27 +429,19 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.sc = L.sc;
     a.nrhs = L.nrhs;
     a.stride = L.stride;
-    a.jacobi = L.jacobi ? 1 : 0;
     const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     const int threads = ras_threads(g, L.overlap);
     if (threads > 1024) return hipErrorInvalidValue;
     dim3 grid(nblk * a.nrhs), block(threads);
     if (ne <= 128) {
-        if (L.link_prec == P32) k_ras<float, 128><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P16) k_ras<__half, 128><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P32C) k_ras<R12f, 128><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P16C) k_ras<R12h, 128><<<grid, block, 0, st>>>(a);
-        else return hipErrorInvalidValue;
-    } else if (ne <= 648) {
-        if (L.link_prec == P32) k_ras<float, 648><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P16) k_ras<__half, 648><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P32C) k_ras<R12f, 648><<<grid, block, 0, st>>>(a);
-        else if (L.link_prec == P16C) k_ras<R12h, 648><<<grid, block, 0, st>>>(a);
-        else return hipErrorInvalidValue;
-    } else {
-        return hipErrorInvalidValue;
+        if (L.jacobi) return ras_dispatch<128, true>(L, a, grid, block, st);
+        return ras_dispatch<128, false>(L, a, grid, block, st);
     }
-    return hipGetLastError();
+    if (ne <= 648) {
+        if (L.jacobi) return ras_dispatch<648, true>(L, a, grid, block, st);
+        return ras_dispatch<648, false>(L, a, grid, block, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace wcl
