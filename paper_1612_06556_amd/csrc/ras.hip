@@ -91,7 +91,15 @@ WCL_D void ras_load(const void *links, int q, const RasSite &S, uint32_t Vh, uin
     if (!in) ln = t;                       // any valid site; its weight is 0
     uint32_t gl = FWD ? S.g : (uint32_t)gnb[ln];
     ras_fence(acc, ln, gl);
-    load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
+    // A cut hop fetches no link (its lanes are masked off): zero link,
+    // weight 0.  For the two-row FP16 links (24 bytes) the masked form
+    // measured slower, and they are loaded for every hop.
+    if constexpr (std::is_same<SL, R12h>::value) {
+        load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
+    } else {
+        if (in) load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
+        else st.u = LinkRaw<SL>{};
+    }
     st.ln = ln;
     st.w = in ? (MU == 3 ? (FWD ? S.sf : S.sb) : 1.f) : 0.f;
 }
