@@ -35,6 +35,34 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 PAPER_KNC_HOP_GFLOPS = 200.0
 
+# Traffic of the RAS kernel from rocprofv3 counters over the bench step:
+# FETCH_SIZE and WRITE_SIZE per working dispatch (KiB), each scaled by what it
+# reads for a 1 GiB device copy (FETCH 524309.3 KiB -> x2.0, WRITE x1.0).
+# FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
+# the kernel sources it was taken on (checked by hash; else traffic is null).
+PMC_TRAFFIC = {
+    "ras": {"fetch_kib": 2138987.8, "fetch_scale": 1048576 / 524309.3125, "write_kib": 82944.2,
+            "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h", "wcl_launch.h"),
+            "sha256": "cf02d76cd0eb3bb4fb3bec6eff19044291f8d26ffb8e903f5399acfbe383afca",
+            "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
+}
+
+
+def pmc_traffic(kclass):
+    """Counter-measured bytes per launch of a kernel class, or None when the
+    counters were not taken on the current sources."""
+    import hashlib
+    t = PMC_TRAFFIC.get(kclass)
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_1612_06556_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    return t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -347,8 +375,16 @@ def main():
     d = stats[dom]
     if dom == "ras":
         achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        traffic = pmc_traffic("ras")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": None if traffic is None else round(traffic)}
+        alg = d["bytes"] / max(d["launches"], 1)
+        roof["algorithmic_bytes_per_launch"] = round(alg)
+        if traffic is not None:
+            # the block data re-read by every minimal-residual step from L2 misses
+            roof["traffic_over_algorithmic"] = round(traffic / alg, 2)
+            roof["l2_miss_GBps"] = round(traffic * d["launches"] / (d["ms"] * 1e-3) / 1e9, 1)
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
