@@ -42,7 +42,7 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
     "ras": {"fetch_kib": 2138987.8, "fetch_scale": 1048576 / 524309.3125, "write_kib": 82944.2,
-            "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h", "wcl_launch.h"),
+            "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h"),
             "sha256": "cf02d76cd0eb3bb4fb3bec6eff19044291f8d26ffb8e903f5399acfbe383afca",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
@@ -119,9 +119,10 @@ def _rate(ms, Vh, flop_site, bytes_site):
 
 def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     """Standalone kernels (median of 5 trials of 200 launches, cold = 4
-    rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set),
-    the copy ceiling, the paper's long lattice, and time-to-solution
-    variants against the plain FP64 solve."""
+    rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set; the
+    FP32 hop also cold with non-temporal link loads), the device's streaming
+    ceilings, the paper's long lattice, and time-to-solution variants against
+    the plain FP64 solve."""
     out = {}
     hop, clov = {}, {}
     for comp in (0, 1):
@@ -135,21 +136,21 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                 if not comp:
                     ms = _median_ms(lambda: lat.bench_clover(prec, 200, copies))
                     clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
+    # single-use (cold) calls with non-temporal link and clover loads
+    lat.set_compression(0)
+    tune = wcl.wcl_autotune_hop(lat.h, 32, 4)
+    wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 1)
+    hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 200, 4)), Vh, 1320, 768)
+    wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     lat.set_compression(1)
+    wcl.wcl_autotune_hop(lat.h, 32, 4)
     out["hop_standalone"] = hop
     out["clover_standalone"] = clov
-    # measured streaming ceiling: device-to-device copy of 2 x 1 GiB
-    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(10):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * src.numel() * 4 / (time.perf_counter() - t1) / 1e9
-    del src, dst
+    # measured streaming ceilings of this device (library kernels, 2 GiB buffers)
+    read_gbs, copy_gbs = wcl.wcl_bench_stream(lat.h, 2048, 10)
+    out["stream_read_GBps"] = round(read_gbs, 1)
     out["copy_ceiling_GBps"] = round(copy_gbs, 1)
+    out["hop_fp32_cold_frac_of_read_ceiling"] = round(hop["fp32_cold"]["GB/s"] / read_gbs, 3)
     out["hop_fp32_cold_frac_of_copy"] = round(hop["fp32_cold"]["GB/s"] / copy_gbs, 3)
     out["hop_fp32_cold_vs_paper_knc_200gflops"] = round(hop["fp32_cold"]["GFlop/s"] / PAPER_KNC_HOP_GFLOPS, 1)
     # the paper's long single-card lattice: FP32 links alone (382 MB) exceed the Infinity Cache

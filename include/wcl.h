@@ -171,6 +171,12 @@ int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_c
  * with the same protocol.  WCL_ESTATE before wcl_set_params. */
 int wcl_bench_clover(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
 
+/* Streaming ceilings of the device, for the roofline: the mean rate of a
+ * read-only pass and of a copy over two buffers of `mib` MiB each (context
+ * workspace; `reps` launches after 10 warm-ups).  *read_gbs = bytes read per
+ * second, *copy_gbs = bytes read + written per second, in GB/s. */
+int wcl_bench_stream(wcl_ctx *ctx, double mib, int reps, double *read_gbs, double *copy_gbs);
+
 /* Kernel-class profiling on the context's stream: with profiling enabled,
  * every launch of the classes below is bracketed by HIP events and its
  * algorithmic HBM bytes and flops are recorded (1320 flop per hop site,

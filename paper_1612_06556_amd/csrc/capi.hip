@@ -1314,6 +1314,29 @@ extern "C" int wcl_bench_clover(wcl_ctx *c, int prec, int reps, int copies, doub
     }, ms);
 }
 
+extern "C" int wcl_bench_stream(wcl_ctx *c, double mib, int reps, double *read_gbs, double *copy_gbs)
+{
+    if (!c || !read_gbs || !copy_gbs) return fail(WCL_EINVAL, "null argument");
+    if (!(mib >= 1.0 && mib <= 65536.0) || reps < 1) return fail(WCL_EINVAL, "1 <= mib <= 65536 and reps >= 1 required");
+    const size_t bytes = ((size_t)(mib * 1048576.0) / 16) * 16, n16 = bytes / 16;
+    const int blocks = 8192;
+    void *a, *b, *out;
+    CHK(wsget(c, S_BENCH, bytes, &a));
+    CHK(wsget(c, S_BENCH + 1, bytes, &b));
+    CHK(wsget(c, S_BENCH + 2, (size_t)blocks * 256 * sizeof(float), &out));
+    HIPCHK(launch_zero(P32, bytes / 8, a, c->st));
+    double ms[2];
+    for (int copy = 0; copy < 2; copy++) {
+        CHK(time_launches(c, reps, 1, [&](int) -> int {
+            HIPCHK(launch_stream(copy, a, b, n16, (float *)out, blocks, c->st));
+            return WCL_OK;
+        }, &ms[copy]));
+    }
+    *read_gbs = bytes / (ms[0] * 1e-3) / 1e9;
+    *copy_gbs = 2.0 * bytes / (ms[1] * 1e-3) / 1e9;
+    return WCL_OK;
+}
+
 extern "C" int wcl_grad(wcl_ctx *c, const double *x, const double *y, double *gU, double *gk)
 {
     if (!c || !x || !y || !gU || !gk) return fail(WCL_EINVAL, "null argument");

@@ -1060,4 +1060,51 @@ void hop_work(const HopLaunch &a, double *bytes, double *flops)
     *flops = f * sites;
 }
 
+// ---------------------------------------------------------------------------
+// Streaming ceilings for the roofline: a read-only pass (8 independent float4
+// loads in flight per thread, one float written per thread) and a copy.
+__global__ void __launch_bounds__(256) k_stream_read(const float4 *__restrict__ a, size_t n, float *out)
+{
+    constexpr int U = 8;
+    float4 s = {0.f, 0.f, 0.f, 0.f};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = a[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            s.x += v[u].x; s.y += v[u].y; s.z += v[u].z; s.w += v[u].w;
+        }
+    }
+    for (; i < n; i += stride) {
+        const float4 v = a[i];
+        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s.x + s.y + s.z + s.w;
+}
+
+__global__ void __launch_bounds__(256) k_stream_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n)
+{
+    constexpr int U = 4;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = a[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; u++) b[i + u * stride] = v[u];
+    }
+    for (; i < n; i += stride) b[i] = a[i];
+}
+
+hipError_t launch_stream(int copy, const void *a, void *b, size_t n16, float *out, int blocks, hipStream_t st)
+{
+    if (copy) k_stream_copy<<<blocks, 256, 0, st>>>((const float4 *)a, (float4 *)b, n16);
+    else k_stream_read<<<blocks, 256, 0, st>>>((const float4 *)a, n16, out);
+    return hipGetLastError();
+}
+
 }  // namespace wcl

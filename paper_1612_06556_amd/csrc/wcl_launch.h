@@ -72,6 +72,9 @@ hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, voi
 // Per-workgroup maxima of the SU(3) defect of the FP64 links (|row2 -
 // conj(row0 x row1)|, |row norm - 1|, |<row0, row1>|) into partial[nblocks].
 hipError_t launch_su3_check(const Geom &g, const void *u64, double *partial, int nblocks, hipStream_t st);
+// Streaming probes over n16 float4 elements: copy = 0 reads a into one float
+// per thread of out[blocks * 256]; copy = 1 copies a to b.
+hipError_t launch_stream(int copy, const void *a, void *b, size_t n16, float *out, int blocks, hipStream_t st);
 // Clover T and T^-1 (FP64 arithmetic) from the FP64 links, written in all
 // three precisions.  info_dev[0] counts sites whose 6x6 block lost positive
 // definiteness during inversion (a zero or negative pivot).

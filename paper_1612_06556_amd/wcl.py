@@ -89,6 +89,8 @@ def load():
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     lib.wcl_set_compression.argtypes = [_vp, ctypes.c_int]
+    lib.wcl_bench_stream.argtypes = [_vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -170,6 +172,12 @@ def wcl_bench_clover(h, prec, reps, copies):
     ms = ctypes.c_double(0.0)
     _check(load().wcl_bench_clover(h, int(prec), int(reps), int(copies), ctypes.byref(ms)))
     return ms.value
+
+
+def wcl_bench_stream(h, mib, reps):
+    r, c = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load().wcl_bench_stream(h, float(mib), int(reps), ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
 
 
 def wcl_destroy(h):

@@ -168,3 +168,13 @@ def test_bench_entry_points():
         assert lat.bench_clover(prec, 5, 3) > 0
     psi = synth.gaussian_spinor(dims, 41)
     assert rel(to_host(lat.apply(to_gpu(psi), prec=32)), orc.D(psi)) <= 1e-6
+
+
+def test_stream_ceiling_entry_point():
+    """wcl_bench_stream returns positive read and copy rates on a small buffer."""
+    from paper_1612_06556_amd import wcl
+    lat, _, _ = setup((8, 8, 8, 8), -1, 0.12, 1.0, 1001, None)
+    r, c = wcl.wcl_bench_stream(lat.h, 16, 3)
+    assert r > 0 and c > 0
+    with pytest.raises(wcl.WclError):
+        wcl.wcl_bench_stream(lat.h, 0.5, 3)
