@@ -32,3 +32,34 @@ def test_library_exports_every_declared_symbol():
     opts = wcl.wcl_default_opts()
     assert opts.tol == 1e-10 and opts.use_ras == 1 and opts.ras_iters == 4
     assert ctypes.sizeof(wcl.wcl_solve_info) == 32
+
+
+def _struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "wcl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
+    return [m.group(2) for m in re.finditer(r"\b(int|double)\s+([a-z_0-9]+)\s*;", body)]
+
+
+@pytest.mark.parametrize("name", ["wcl_solve_opts", "wcl_solve_info", "wcl_kstat"])
+def test_binding_structs_match_the_header(name):
+    """The ctypes structures list the header's fields in the header's order."""
+    from paper_1612_06556_amd import wcl
+    fields = [f for f, _ in getattr(wcl, name)._fields_]
+    assert fields == _struct_fields(name)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_1612_06556_amd import wcl
+    monkeypatch.setattr(wcl, "LIB_PATH", os.path.join(ROOT, "no_such_libwcl.so"))
+    monkeypatch.setattr(wcl, "_lib", None)
+    with pytest.raises(RuntimeError):
+        wcl.load()
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -234,3 +234,11 @@ def test_mixed_structure_solvers_reach_the_solution(use_ras):
     assert ii["status"] == 0
     assert rel(o.schur(xi), bh / np.linalg.norm(bh)) < 1e-5 * 1.0001
     assert np.abs(xi[~even]).max() == 0.0
+
+
+def test_ras_rejects_unknown_block_solver():
+    dims = (8, 8, 8, 8)
+    o = oracle.Oracle(dims, -1, 0.125, 1.0, synth.su3_field(dims, 3))
+    v = synth.gaussian_spinor(dims, 4)
+    with pytest.raises(ValueError):
+        o.ras(v, (4, 4, 4, 4), 1, 4, 2)
