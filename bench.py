@@ -43,7 +43,7 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 PMC_TRAFFIC = {
     "ras": {"fetch_kib": 2138987.8, "fetch_scale": 1048576 / 524309.3125, "write_kib": 82944.2,
             "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h"),
-            "sha256": "cf02d76cd0eb3bb4fb3bec6eff19044291f8d26ffb8e903f5399acfbe383afca",
+            "sha256": "92f401db88d83f38935ca0c09435278b910114fb3818d114a16b6a426c93a493",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
