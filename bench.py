@@ -118,7 +118,7 @@ def _rate(ms, Vh, flop_site, bytes_site):
 
 
 def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
-    """Standalone kernels (median of 5 trials of 200 launches, cold = 4
+    """Standalone kernels (median of 5 trials of 1000 launches, cold = 4
     rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set; the
     FP32 hop also cold with non-temporal link loads), the device's streaming
     ceilings, the paper's long lattice, and time-to-solution variants against
@@ -130,17 +130,17 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
         for prec in (32, 16):
             link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
             for copies, tag in ((4, "cold"), (1, "hot")):
-                ms = _median_ms(lambda: lat.bench_hop(prec, 200, copies))
+                ms = _median_ms(lambda: lat.bench_hop(prec, 1000, copies))
                 name = f"fp{prec}{'_r12' if comp else ''}_{tag}"
                 hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
                 if not comp:
-                    ms = _median_ms(lambda: lat.bench_clover(prec, 200, copies))
+                    ms = _median_ms(lambda: lat.bench_clover(prec, 1000, copies))
                     clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
     # single-use (cold) calls with non-temporal link and clover loads
     lat.set_compression(0)
     tune = wcl.wcl_autotune_hop(lat.h, 32, 4)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 1)
-    hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 200, 4)), Vh, 1320, 768)
+    hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 1000, 4)), Vh, 1320, 768)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     lat.set_compression(1)
     wcl.wcl_autotune_hop(lat.h, 32, 4)

@@ -6,6 +6,7 @@ Iteration counts are reported, not compared (they depend on rounding)."""
 import numpy as np
 import pytest
 
+import oracle
 from gpu_util import rel, setup, to_gpu, to_host
 from paper_1612_06556_amd import synth
 
@@ -103,6 +104,32 @@ def test_mixed_ras_16x32():
     err = rel(x, _reference(orc, b, "16"))
     print(f"x error vs oracle {err:.3e}", flush=True)
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("inner_prec", [32, 16])
+def test_bench_solve_24x32(inner_prec):
+    """The benchmark's solve at 24^3x32, kappa 0.126 (two-row links, FP64 flexible
+    BiCGStab + RAS-BiCGStab): true residual <= 1e-10 by the oracle's D and x
+    within 1e-8 of the oracle's solution converged to 1e-13."""
+    import torch
+    from paper_1612_06556_amd import wcl
+    dims = (24, 24, 24, 32)
+    U = synth.su3_field(dims, 1003)
+    lat = wcl.Lattice(dims, -1)
+    lat.set_compression(1)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    lat.set_params(0.126, 1.0)
+    orc = oracle.Oracle(dims, -1, 0.126, 1.0, U)
+    b = synth.gaussian_spinor(dims, 2003)
+    x, info, rc = lat.solve(to_gpu(b), tol=1e-10, inner_tol=1e-2, use_ras=1, inner_prec=inner_prec)
+    x = to_host(x)
+    print(f"bench solve 24^3x32 prec={inner_prec}", info, flush=True)
+    assert rc == 0
+    assert _oracle_residual(orc, x, b) <= 1e-10
+    err = rel(x, _reference(orc, b, "24"))
+    print(f"x error vs oracle {err:.3e}", flush=True)
+    assert err <= 1e-8
+    lat.close()
 
 
 def test_solve_edge_cases():
