@@ -343,7 +343,9 @@ def main():
     # launch shape of the hopping kernel (project autotuner, untimed)
     tuning = wcl.wcl_autotune_hop(lat.h, 32, 4)
 
-    opts = dict(tol=1e-10, use_ras=1, ras_overlap=1, ras_iters=4, inner_prec=32, inner_tol=1e-2,
+    # inner relative tolerance 0.1: the paper passes one without a value; the
+    # sweep (--sweep) finds 0.1 the fastest of 1e-1 ... 1e-4 for this solve
+    opts = dict(tol=1e-10, use_ras=1, ras_overlap=1, ras_iters=4, inner_prec=32, inner_tol=1e-1,
                 outer=wcl.OUTER_FBICGSTAB)
 
     def step():
@@ -407,8 +409,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "24^3x32 Wilson-Clover solve to 1e-10: FP64 flexible BiCGStab + FP32 "
-                               "RAS-BiCGStab (4^4 cores, overlap 1, 4 MR, two-row SU(3) links), incl. gauge "
-                               "ingest and clover build",
+                               "RAS-BiCGStab (4^4 cores, overlap 1, 4 MR, two-row SU(3) links, inner tol 0.1), "
+                               "incl. gauge ingest and clover build",
                    "lattice": "24x24x24x32", "kappa": KAPPA, "csw": CSW, "t_bc": "antiperiodic",
                    "gauge": "reunitarised exp(0.3 i H), seed 1003", "source": "Gaussian, seed 2003",
                    "tuning": tuning},
