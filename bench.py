@@ -80,31 +80,41 @@ def parse():
 
 
 def cpu_baseline(U, psi, budget_s=12.0):
-    """The FP64 oracle's full-lattice D apply on the host cores (bounded
-    sample), then on one thread for a third of the budget."""
+    """The FP64 oracle on the host cores (bounded samples): the full-lattice D
+    apply at 24^3x32 on all cores and on one thread, the hopping term alone,
+    and a plain FP64 BiCGStab solve at 8^4."""
     import oracle
+    from paper_1612_06556_amd import synth
     V = int(np.prod(DIMS))
 
-    def run(budget):
-        orc = oracle.Oracle(DIMS, -1, KAPPA, CSW, U)
+    def run(fn, budget):
         n = 0
         t0 = time.perf_counter()
         while True:
-            orc.D(psi)
+            fn(psi)
             n += 1
             el = time.perf_counter() - t0
             if el >= budget or n >= 400:
                 return n, el
 
     threads = oracle.set_threads(0)
-    n, el = run(budget_s)
+    orc = oracle.Oracle(DIMS, -1, KAPPA, CSW, U)
+    n, el = run(orc.D, budget_s)
     flops = n * V * (1320.0 + 504.0 + 48.0)
+    nh, elh = run(orc.hop, budget_s / 4)
     oracle.set_threads(1)
-    n1, el1 = run(budget_s / 3)
+    n1, el1 = run(orc.D, budget_s / 3)
     oracle.set_threads(threads)
+    d8 = (8, 8, 8, 8)
+    o8 = oracle.Oracle(d8, -1, 0.12, CSW, synth.su3_field(d8, 1001))
+    t0 = time.perf_counter()
+    _, info = o8.bicgstab_full(synth.gaussian_spinor(d8, 2001), 1e-10, 10000)
+    t8 = time.perf_counter() - t0
     return {"value": round(flops / el / 1e9, 3), "unit": "GFlop/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} full-lattice FP64 D applications at 24^3x32 (1872 flop/site), {el:.1f} s",
-            "single_thread_value": round(n1 * V * 1872.0 / el1 / 1e9, 3)}
+            "single_thread_value": round(n1 * V * 1872.0 / el1 / 1e9, 3),
+            "hop_value": round(nh * V * 1320.0 / elh / 1e9, 3),
+            "plain_fp64_8x8x8x8": {"ms": round(t8 * 1e3, 1), "iters": info["iters"], "relres": info["relres"]}}
 
 
 def _median_ms(fn, trials=5):
