@@ -182,6 +182,7 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     variants = (("mixed_ras_fp32", opts, 1),
                 ("mixed_ras_fp32_full_links", opts, 0),
                 ("mixed_ras_fp32_graph", dict(opts, use_graph=1), 1),
+                ("mixed_ras_fp32_dc", dict(opts, outer=wcl.OUTER_DC), 1),
                 ("mixed_ras_fp16", dict(opts, inner_prec=16), 1),
                 ("mixed_noras_fp32", dict(opts, use_ras=0), 1),
                 ("mixed_noras_fp32_full_links", dict(opts, use_ras=0), 0),
