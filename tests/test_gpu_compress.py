@@ -137,3 +137,18 @@ def test_bench_shape_24x32_compressed():
         ms = lat.bench_hop(prec, 50, 4)
         print(f"hop12 prec={prec} cold {ms * 1e3:.2f} us", flush=True)
         assert ms > 0
+
+
+def test_long_lattice_24x96():
+    """The paper's long single-card lattice 24^3x96 (links beyond the Infinity
+    Cache): two-row FP32 / FP16 D against the oracle."""
+    dims = (24, 24, 24, 96)
+    lat, U = _lattice(dims, -1, 0.126, 1.0, 1006, None)
+    orc = oracle.Oracle(dims, -1, 0.126, 1.0, U)
+    psi = synth.gaussian_spinor(dims, 2006)
+    ref = orc.D(psi)
+    g = to_gpu(psi)
+    for prec in (32, 16):
+        e = rel(to_host(lat.apply(g, prec=prec)), ref)
+        print(f"D12 24^3x96 prec={prec} rel={e:.3e}", flush=True)
+        assert e <= TOL[prec]
