@@ -161,7 +161,8 @@ int wcl_solve(wcl_ctx *ctx, const double *b_dev, double *x_dev, int nrhs, const 
  * 2 dL/d conj(U) (PyTorch's convention), *gkappa_host dL/dkappa. */
 int wcl_grad(wcl_ctx *ctx, const double *x_dev, const double *y_dev, double *gU_dev, double *gkappa_host);
 
-/* Time the standalone even/odd hopping kernel H_eo (FP32 or FP16 links):
+/* Time the standalone even/odd hopping kernel H_eo (FP32 or FP16 links, two-row
+ * when compression is on; FP32 spinors):
  * `reps` launches after 10 warm-ups, rotating over `copies` independent sets
  * of links and spinors (copies >= 1; more copies defeat the 256 MB Infinity
  * Cache).  *ms_per_call receives the mean launch time from HIP events. */
