@@ -301,14 +301,17 @@ def sweep(opts, torch, synth, wcl):
     batch = {}
     for name, kw in (("ras_fp16", dict(opts, inner_prec=16)), ("noras_fp16", dict(opts, use_ras=0, inner_prec=16))):
         r12 = _timed_solve(lat, b, torch, runs=1, **kw)
+        wcl.wcl_set_batch_tuning(lat.h, 4)
+        r12r = _timed_solve(lat, b, torch, runs=1, **kw)
+        wcl.wcl_set_batch_tuning(lat.h, 1)
         t1 = time.perf_counter()
         for k in range(12):
             lat.solve(b[k], **kw)
         torch.cuda.synchronize()
         seq = (time.perf_counter() - t1) * 1e3
-        batch[name] = {"batched_12_ms": r12["ms"], "sequential_12_ms": round(seq, 1),
-                       "per_propagator_ms": round(r12["ms"] / 12, 2), "GFlop/s": r12["GFlop/s"],
-                       "inner": r12["inner"]}
+        batch[name] = {"batched_12_ms": r12["ms"], "batched_12_ms_4_rhs_per_thread": r12r["ms"],
+                       "sequential_12_ms": round(seq, 1), "per_propagator_ms": round(r12["ms"] / 12, 2),
+                       "GFlop/s": r12["GFlop/s"], "inner": r12["inner"]}
     t1 = time.perf_counter()
     for k in range(2):
         lat.solve(b[k], tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000)

@@ -205,6 +205,12 @@ int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
  * (may be NULL) receives {block, depth, xcd}. */
 int wcl_set_tuning(wcl_ctx *ctx, int hop_block, int hop_depth, int hop_xcd, int hop_nontemporal);
 int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
+/* Batched launches (nrhs > 1) of the FP32-vector hopping kernels (the inner
+ * solver's Schur halves): rhs_per_thread = 1 gives each right-hand side its
+ * own workgroups (links shared through L2); 2 or 4 keep that many right-hand
+ * sides in one thread's registers, so every link and clover block loaded
+ * serves all of them.  WCL_EINVAL for other values. */
+int wcl_set_batch_tuning(wcl_ctx *ctx, int rhs_per_thread);
 
 const char *wcl_last_error(void);
 int wcl_destroy(wcl_ctx *ctx);

@@ -70,6 +70,7 @@ struct wcl_ctx {
     int cap = 0;                // right-hand sides the scalar and partial buffers hold
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
     int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0;
+    int hop_rhs = 1;   // right-hand sides per thread in batched launches (1, 2, 4)
     // event profiling of kernel classes
     struct Rec {
         int kclass;
@@ -157,6 +158,7 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     L.xcd = c->hop_xcd;
     L.block = c->hop_block;
     L.depth = c->hop_depth;
+    L.rhs_per_thread = c->hop_rhs;
     L.nontemporal = c->hop_nt;
     return L;
 }
@@ -1427,6 +1429,15 @@ extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_
     c->hop_depth = hop_depth;
     c->hop_xcd = hop_xcd ? 1 : 0;
     c->hop_nt = hop_nontemporal ? 1 : 0;
+    return WCL_OK;
+}
+
+extern "C" int wcl_set_batch_tuning(wcl_ctx *c, int rhs_per_thread)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    if (rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4)
+        return fail(WCL_EINVAL, "rhs_per_thread must be 1, 2 or 4");
+    c->hop_rhs = rhs_per_thread;
     return WCL_OK;
 }
 

@@ -566,6 +566,149 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides per thread (batched inner solves): each link and
+// clover block is loaded once into registers and applied to the NR
+// right-hand sides of a group, whose neighbour spinors are loaded together.
+// FP32 spinors; modes HOP, CLOV_H, XPAY; no dagger.  A right-hand side whose
+// scalars say done is neither computed nor stored.
+template <typename SL, int K, int NR>
+WCL_D void hop_mr_hop(const HopArgs &a, const Site &s, uint32_t h0, const bool act[NR], const char *const in[NR],
+                      cplx<float> acc[NR][12])
+{
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
+    constexpr int S = FWD ? -1 : 1;
+    const Geom &g = a.g;
+    const uint32_t Vh = g.Vh;
+    uint32_t hn = (uint32_t)neighbour(g, s, MU, FWD ? +1 : -1);
+    uint32_t h = h0;
+    // this hop's loads wait for the previous hop's work on the first group member
+    pipeline_fence(acc[0], hn, h);
+    LinkRaw<SL> lr;
+    if (FWD) load_link_raw<SL>(a.links, MU, a.p, h, Vh, lr);
+    else load_link_raw<SL>(a.links, MU, 1 - a.p, hn, Vh, lr);
+    cplx<float> psi[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+        if (act[r]) load_spinor<float, float>(in[r], hn, Vh, psi[r]);
+    float sign = 1.f;
+    if (MU == 3 && g.tbc < 0 && s.x[3] == (FWD ? g.L[3] - 1 : 0)) sign = -1.f;
+    cplx<float> u[9];
+    expand_link<SL, float>(lr, u);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (!act[r]) continue;
+        cplx<float> hh[6], uh[6];
+        project<MU, S, float>(psi[r], hh);
+        if (MU == 3) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) hh[k] = sign * hh[k];
+        }
+        if (FWD) su3_mul(u, hh, uh);
+        else su3_dag_mul(u, hh, uh);
+        accumulate<MU, S, float>(acc[r], uh);
+    }
+}
+
+template <typename SL, int K, int NR>
+WCL_D void hop_mr_all(const HopArgs &a, const Site &s, uint32_t h, const bool act[NR], const char *const in[NR],
+                      cplx<float> acc[NR][12])
+{
+    if constexpr (K < 8) {
+        hop_mr_hop<SL, K, NR>(a, s, h, act, in, acc);
+        hop_mr_all<SL, K + 1, NR>(a, s, h, act, in, acc);
+    }
+}
+
+template <typename SL, int MODE, int NR>
+__global__ void __launch_bounds__(256) k_hop_mr(HopArgs a)
+{
+    // workgroup id = site block * groups + group (the groups of one site block
+    // run back to back on one XCD, so L2 serves the links to all of them)
+    const int ngr = (a.nrhs + NR - 1) / NR;
+    const int lin = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int grp = lin % ngr;
+    const int bid = lin / ngr;
+    const int r0 = grp * NR;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = (r0 + r < a.nrhs) && !(a.sc && a.sc[r0 + r].done);
+        any = any || act[r];
+    }
+    if (!any) return;
+    const int h = bid * blockDim.x + threadIdx.x;
+    if (h >= a.g.Vh) return;
+    const uint32_t Vh = a.g.Vh;
+    const char *in[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) in[r] = (const char *)a.in + (act[r] ? r0 + r : 0) * a.in_stride;
+    const Site s = decompose(a.g, h, a.p);
+    cplx<float> acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int i = 0; i < 12; i++) acc[r][i] = {0.f, 0.f};
+    hop_mr_all<SL, 0, NR>(a, s, h, act, in, acc);
+
+    if constexpr (MODE == HOP) {
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            if (act[r]) store_spinor<float, float>((char *)a.out + (r0 + r) * a.out_stride, h, Vh, acc[r]);
+    } else {
+        // one clover chirality block at a time, shared by the group
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            float c[36];
+            load_clover_half<typename ClovS<SL>::T, float>(a.clov, a.p, h, Vh, half, c);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (!act[r]) continue;
+                cplx<float> o[6];
+                clover_mul_half(c, acc[r] + 6 * half, o);
+                char *out = (char *)a.out + (r0 + r) * a.out_stride;
+                if constexpr (MODE == XPAY) {
+                    const char *x = (const char *)a.x + (r0 + r) * a.x_stride;
+                    const float cf = (float)a.coef;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const float4 xv = ldf<float4>(x, ((3 * half + k) * Vh + h) * 16u);
+                        o[2 * k] = {fmaf(cf, o[2 * k].re, xv.x), fmaf(cf, o[2 * k].im, xv.y)};
+                        o[2 * k + 1] = {fmaf(cf, o[2 * k + 1].re, xv.z), fmaf(cf, o[2 * k + 1].im, xv.w)};
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; k++)
+                    stf(out, ((3 * half + k) * Vh + h) * 16u,
+                        make_float4(o[2 * k].re, o[2 * k].im, o[2 * k + 1].re, o[2 * k + 1].im));
+            }
+        }
+    }
+}
+
+template <typename SL, int NR>
+static hipError_t hop_mr_dispatch(const HopLaunch &L, const HopArgs &a, dim3 block, hipStream_t st)
+{
+    const int ngr = (a.nrhs + NR - 1) / NR;
+    dim3 grid(((a.g.Vh + block.x - 1) / block.x) * ngr);
+    switch (L.mode) {
+    case HOP: k_hop_mr<SL, HOP, NR><<<grid, block, 0, st>>>(a); break;
+    case CLOV_H: k_hop_mr<SL, CLOV_H, NR><<<grid, block, 0, st>>>(a); break;
+    case XPAY: k_hop_mr<SL, XPAY, NR><<<grid, block, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename SL>
+static hipError_t hop_mr_nr(const HopLaunch &L, const HopArgs &a, dim3 block, hipStream_t st)
+{
+    if (L.rhs_per_thread == 4) return hop_mr_dispatch<SL, 4>(L, a, block, st);
+    return hop_mr_dispatch<SL, 2>(L, a, block, st);
+}
+
 // Pipeline-depth variants (hops whose operands are in flight: 2, 3) times
 // temporal / non-temporal operator loads.  D^dag launches use depth 2.
 template <typename SL, typename SS, int MODE>
@@ -616,6 +759,16 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
     if (bs > 256 || bs % 64) return hipErrorInvalidValue;
     dim3 grid(((a.g.Vh + bs - 1) / bs) * a.nrhs);
     dim3 block(bs);
+    if ((L.rhs_per_thread == 2 || L.rhs_per_thread == 4) && a.nrhs >= 2 && L.spin_prec == P32 && !L.dagger &&
+        L.mode != CLOVX) {
+        switch (L.link_prec) {
+        case P32: return hop_mr_nr<float>(L, a, block, st);
+        case P16: return hop_mr_nr<__half>(L, a, block, st);
+        case P32C: return hop_mr_nr<R12f>(L, a, block, st);
+        case P16C: return hop_mr_nr<R12h>(L, a, block, st);
+        default: break;
+        }
+    }
     if (L.link_prec == P64 && L.spin_prec == P64) hop_dispatch_mode<double, double>(L, a, grid, block, st);
     else if (L.link_prec == P32 && L.spin_prec == P32) hop_dispatch_mode<float, float>(L, a, grid, block, st);
     else if (L.link_prec == P16 && L.spin_prec == P32) hop_dispatch_mode<__half, float>(L, a, grid, block, st);

@@ -89,6 +89,7 @@ def load():
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     lib.wcl_set_compression.argtypes = [_vp, ctypes.c_int]
+    lib.wcl_set_batch_tuning.argtypes = [_vp, ctypes.c_int]
     lib.wcl_bench_stream.argtypes = [_vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     _lib = lib
@@ -197,6 +198,10 @@ def wcl_profile_read(h, kclass):
 
 def wcl_set_tuning(h, hop_block, hop_depth, hop_xcd, hop_nontemporal=0):
     _check(load().wcl_set_tuning(h, int(hop_block), int(hop_depth), int(hop_xcd), int(hop_nontemporal)))
+
+
+def wcl_set_batch_tuning(h, rhs_per_thread):
+    _check(load().wcl_set_batch_tuning(h, int(rhs_per_thread)))
 
 
 def wcl_autotune_hop(h, prec, copies):

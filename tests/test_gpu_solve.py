@@ -268,3 +268,30 @@ def test_graph_replay_matches_eager():
         assert rc0 == 0 and rc1 == 0
         assert np.array_equal(to_host(x0), to_host(x1))
         assert [i["inner_iters_total"] for i in i0] == [i["inner_iters_total"] for i in i1]
+
+
+@pytest.mark.parametrize("inner_prec,use_ras", [(32, 1), (16, 0)])
+def test_batch_rhs_per_thread(inner_prec, use_ras):
+    """Keeping 2 or 4 right-hand sides per thread in the batched Schur halves
+    (a different kernel, so FP32 rounding may differ): every right-hand side
+    reaches the oracle's residual bound and agrees with the one-per-workgroup
+    solve to the solution tolerance."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    b = synth.gaussian_spinor(dims, 51, nrhs=5)   # a ragged last group of 4
+    xs = []
+    try:
+        for nr in (1, 2, 4):
+            wcl.wcl_set_batch_tuning(lat.h, nr)
+            x, infos, rc = lat.solve(to_gpu(b), tol=1e-10, inner_prec=inner_prec, use_ras=use_ras)
+            assert rc == 0
+            xs.append(to_host(x))
+    finally:
+        wcl.wcl_set_batch_tuning(lat.h, 1)
+    for k in range(5):
+        for j in (1, 2):
+            assert _oracle_residual(orc, xs[j][k], b[k]) <= 1e-10
+            assert rel(xs[j][k], xs[0][k]) <= 1e-8
+    with pytest.raises(wcl.WclError):
+        wcl.wcl_set_batch_tuning(lat.h, 3)
