@@ -135,6 +135,8 @@ typedef struct {
     int check_every;     /* inner iterations between host convergence checks         */
     int adjoint;         /* 1: solve D^dag x = b instead, as x = g5 D^-1 (g5 b)      */
     int ras_solver;      /* WCL_RAS_MR or WCL_RAS_JACOBI (block solver of the RAS)   */
+    int inner_vec_prec;  /* 32, or 16: the inner solver's vectors stored in FP16 (FP32
+                          * arithmetic; needs inner_prec 16)                        */
 } wcl_solve_opts;
 
 typedef struct {
@@ -147,7 +149,8 @@ typedef struct {
 } wcl_solve_info;
 
 /* Fill opts with the defaults: tol 1e-10, FBICGSTAB, RAS on (overlap 1,
- * 4 iterations), inner_tol 1e-2, FP32 inner, 100 outer, 500 inner. */
+ * 4 iterations, minimal residual), inner_tol 1e-2, FP32 inner links and
+ * vectors, 100 outer, 500 inner. */
 void wcl_default_opts(wcl_solve_opts *opts);
 
 /* Solve D x = b for nrhs right-hand sides (one after another, sharing the

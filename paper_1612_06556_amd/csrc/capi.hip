@@ -694,6 +694,7 @@ void wcl_default_opts(wcl_solve_opts *o)
     o->ras_overlap = 1;
     o->ras_iters = 4;
     o->ras_solver = WCL_RAS_MR;
+    o->inner_vec_prec = 32;
     o->inner_prec = 32;
     o->use_graph = 0;
     o->check_every = 8;
@@ -738,6 +739,7 @@ int get_ws(wcl_ctx *c, SolveWs &w, bool inner, bool plain, int n)
 
 struct InnerCfg {
     int lprec;
+    int vprec;                     // storage of the inner vectors (P32, or P16 with FP16 links)
     double tol;
     int maxit;
     bool ras;
@@ -752,8 +754,8 @@ struct InnerCfg {
 int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, int n)
 {
     const size_t m = 12 * (size_t)c->Vh;   // complex numbers per right-hand side
-    const int lp = cfg.lprec;
-    HIPCHK(launch_bicg_p(P32, m, w.r32, w.p32, w.v32, sc, c->st, n, m));
+    const int lp = cfg.lprec, vp = cfg.vprec;
+    HIPCHK(launch_bicg_p(vp, m, w.r32, w.p32, w.v32, sc, c->st, n, m));
     void *ph = w.p32, *sh = w.s32;
     RasLaunch R{};
     if (cfg.ras) {
@@ -767,35 +769,36 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         R.kappa2 = (float)(c->kappa * c->kappa);
         R.sc = sc;
         R.nrhs = n;
-        R.stride = half_bytes(P32, c->Vh);
+        R.stride = half_bytes(vp, c->Vh);
+        R.vec_prec = vp;
         R.in = w.p32;
         R.out = w.ph32;
         CHK(run_ras(c, R));
         ph = w.ph32;
     }
-    CHK(schur(c, lp, P32, ph, w.v32, w.o32, sc, n));
+    CHK(schur(c, lp, vp, ph, w.v32, w.o32, sc, n));
     {
         const void *a[1] = {w.rt32}, *b[1] = {w.v32};
-        HIPCHK(launch_dots(P32, m, 1, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_dots(vp, m, 1, a, b, c->partials, sc, c->st, n, m));
         HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n));
     }
-    HIPCHK(launch_bicg_s(P32, m, w.r32, w.v32, w.s32, sc, c->st, n, m));
+    HIPCHK(launch_bicg_s(vp, m, w.r32, w.v32, w.s32, sc, c->st, n, m));
     if (cfg.ras) {
         R.in = w.s32;
         R.out = w.sh32;
         CHK(run_ras(c, R));
         sh = w.sh32;
     }
-    CHK(schur(c, lp, P32, sh, w.t32, w.o32, sc, n));
+    CHK(schur(c, lp, vp, sh, w.t32, w.o32, sc, n));
     {
         const void *a[2] = {w.t32, w.t32}, *b[2] = {w.s32, w.t32};
-        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m));
         HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n));
     }
-    HIPCHK(launch_bicg_xr(P32, m, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st, n, m));
+    HIPCHK(launch_bicg_xr(vp, m, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st, n, m));
     {
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, sc, c->st, n, m));
+        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m));
         HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n));
     }
     return WCL_OK;
@@ -812,14 +815,15 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
     Scalars *sc = SI(c);
     const int sstride = (int)(sizeof(Scalars) / sizeof(double));
     CHK(norms_dev(c, P64, m, in64, m, n, sc));
-    HIPCHK(launch_convert(P64, P32, n * Vh, Vh, Vh, in64, w.r32, &sc->t[0], 1, 1.0, c->st, 1, sstride));
-    HIPCHK(launch_copy(P32, n * m, w.r32, w.rt32, c->st));
-    HIPCHK(launch_zero(P32, n * m, w.x32, c->st));
-    HIPCHK(launch_zero(P32, n * m, w.p32, c->st));
-    HIPCHK(launch_zero(P32, n * m, w.v32, c->st));
+    const int vp = cfg.vprec;
+    HIPCHK(launch_convert(P64, vp, n * Vh, Vh, Vh, in64, w.r32, &sc->t[0], 1, 1.0, c->st, 1, sstride));
+    HIPCHK(launch_copy(vp, n * m, w.r32, w.rt32, c->st));
+    HIPCHK(launch_zero(vp, n * m, w.x32, c->st));
+    HIPCHK(launch_zero(vp, n * m, w.p32, c->st));
+    HIPCHK(launch_zero(vp, n * m, w.v32, c->st));
     {
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(P32, m, 2, a, b, c->partials, nullptr, c->st, n, m));
+        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, nullptr, c->st, n, m));
         HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st, n, SF(c)));
     }
     // Iterations are queued in chunks; every kernel of an iteration queued
@@ -887,7 +891,7 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
         const size_t end = (q + 1 < rec_mark.size()) ? rec_mark[q + 1] : c->recs.size();
         for (size_t r = rec_mark[q]; r < end; r++) c->recs[r].bytes = c->recs[r].flops = 0.0;
     }
-    HIPCHK(launch_convert(P32, P64, n * Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st, 1, sstride));
+    HIPCHK(launch_convert(vp, P64, n * Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st, 1, sstride));
     return WCL_OK;
 }
 
@@ -1135,6 +1139,9 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         return fail(WCL_EINVAL, "tol, inner_tol > 0 and iteration limits >= 1 required");
     if (o.outer < 0 || o.outer > WCL_OUTER_PLAIN64_EO) return fail(WCL_EINVAL, "unknown outer solver");
     if (o.inner_prec != 32 && o.inner_prec != 16) return fail(WCL_EINVAL, "inner_prec must be 32 or 16");
+    if (o.inner_vec_prec != 32 && o.inner_vec_prec != 16) return fail(WCL_EINVAL, "inner_vec_prec must be 32 or 16");
+    if (o.inner_vec_prec == 16 && o.inner_prec != 16)
+        return fail(WCL_EINVAL, "FP16 inner vectors need the FP16 links and clover (inner_prec 16)");
     if (o.check_every < 1) o.check_every = 8;
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
     const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
@@ -1156,7 +1163,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
             if (*s) (void)hipStreamDestroy(*s);
         }
     } guard{&graph_exec, &cap_stream};
-    InnerCfg cfg{o.inner_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every,
+    InnerCfg cfg{o.inner_prec, o.inner_vec_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every,
                  o.use_graph != 0 && inner, &graph_exec, cap_stream};
     // the inner stopping threshold is fixed for the whole solve
     for (int k = 0; k < n; k++) {

@@ -888,10 +888,20 @@ WCL_D void block_sum(double v[NV], double *lds /* [NV][16] */)
     }
 }
 
+// Storage of one complex number (V) and the arithmetic type (C) of the
+// flat-vector kernels: FP16 vectors are stored as half2 and computed in FP32.
 template <typename T>
 struct CT;
-template <> struct CT<double> { using V = double2; };
-template <> struct CT<float> { using V = float2; };
+template <> struct CT<double> { using V = double2; using C = double; };
+template <> struct CT<float> { using V = float2; using C = float; };
+template <> struct CT<__half> { using V = __half2; using C = float; };
+
+WCL_D double2 ldv(const double2 &v) { return v; }
+WCL_D float2 ldv(const float2 &v) { return v; }
+WCL_D float2 ldv(const __half2 &v) { return __half22float2(v); }
+WCL_D void stv(double2 &d, double x, double y) { d = make_double2(x, y); }
+WCL_D void stv(float2 &d, float x, float y) { d = make_float2(x, y); }
+WCL_D void stv(__half2 &d, float x, float y) { d = __floats2half2_rn(x, y); }
 
 // partials[rhs][(2*k + {0,1}) * RED_BLOCKS + block] = (Re, Im) of sum conj(a_k) b_k
 // over the rhs-th slice (stride elements apart); blockIdx.y = rhs.
@@ -912,7 +922,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, size_t stride, c
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NP; k++) {
-            const auto x = A[k][i], y = B[k][i];
+            const auto x = ldv(A[k][i]), y = ldv(B[k][i]);
             v[2 * k] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
             v[2 * k + 1] += (double)x.x * (double)y.y - (double)x.y * (double)y.x;
         }
@@ -943,6 +953,10 @@ hipError_t launch_dots(int prec, size_t n, int np, const void *const *a, const v
         if (np == 1) WCL_DOTS(float, 1);
         else if (np == 2) WCL_DOTS(float, 2);
         else WCL_DOTS(float, 3);
+    } else if (prec == P16) {
+        if (np == 1) WCL_DOTS(__half, 1);
+        else if (np == 2) WCL_DOTS(__half, 2);
+        else WCL_DOTS(__half, 3);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1043,13 +1057,14 @@ __global__ void __launch_bounds__(256) k_bicg_p(size_t n, size_t stride, const t
     cdiv(sc->alpha, sc->omega, q2);
     beta[0] = q1[0] * q2[0] - q1[1] * q2[1];
     beta[1] = q1[0] * q2[1] + q1[1] * q2[0];
-    const T br = (T)beta[0], bi = (T)beta[1], wr = (T)sc->omega[0], wi = (T)sc->omega[1];
+    using C = typename CT<T>::C;
+    const C br = (C)beta[0], bi = (C)beta[1], wr = (C)sc->omega[0], wi = (C)sc->omega[1];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const auto pv = p[i], vv = v[i], rv = r[i];
+        const auto pv = ldv(p[i]), vv = ldv(v[i]), rv = ldv(r[i]);
         // d = p - omega v
-        const T dr = pv.x - (wr * vv.x - wi * vv.y);
-        const T di = pv.y - (wr * vv.y + wi * vv.x);
-        p[i] = {rv.x + br * dr - bi * di, rv.y + br * di + bi * dr};
+        const C dr = pv.x - (wr * vv.x - wi * vv.y);
+        const C di = pv.y - (wr * vv.y + wi * vv.x);
+        stv(p[i], rv.x + br * dr - bi * di, rv.y + br * di + bi * dr);
     }
 }
 
@@ -1061,10 +1076,11 @@ __global__ void __launch_bounds__(256) k_bicg_s(size_t n, size_t stride, const t
     if (sc->done) return;
     const size_t off = blockIdx.y * stride;
     r += off; v += off; s += off;
-    const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1];
+    using C = typename CT<T>::C;
+    const C ar = (C)sc->alpha[0], ai = (C)sc->alpha[1];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const auto rv = r[i], vv = v[i];
-        s[i] = {rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x)};
+        const auto rv = ldv(r[i]), vv = ldv(v[i]);
+        stv(s[i], rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
     }
 }
 
@@ -1078,12 +1094,13 @@ __global__ void __launch_bounds__(256) k_bicg_xr(size_t n, size_t stride, typena
     if (sc->done) return;
     const size_t off = blockIdx.y * stride;
     x += off; ph += off; sh += off; r += off; s += off; t += off;
-    const T ar = (T)sc->alpha[0], ai = (T)sc->alpha[1], wr = (T)sc->omega[0], wi = (T)sc->omega[1];
+    using C = typename CT<T>::C;
+    const C ar = (C)sc->alpha[0], ai = (C)sc->alpha[1], wr = (C)sc->omega[0], wi = (C)sc->omega[1];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const auto xv = x[i], pv = ph[i], sv = sh[i], s2 = s[i], tv = t[i];
-        x[i] = {xv.x + (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y),
-                xv.y + (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x)};
-        r[i] = {s2.x - (wr * tv.x - wi * tv.y), s2.y - (wr * tv.y + wi * tv.x)};
+        const auto xv = ldv(x[i]), pv = ldv(ph[i]), sv = ldv(sh[i]), s2 = ldv(s[i]), tv = ldv(t[i]);
+        stv(x[i], xv.x + (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y),
+            xv.y + (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x));
+        stv(r[i], s2.x - (wr * tv.x - wi * tv.y), s2.y - (wr * tv.y + wi * tv.x));
     }
 }
 
@@ -1096,41 +1113,45 @@ static dim3 blas_grid(size_t n, int nrhs = 1)
     return dim3((unsigned)b, nrhs);
 }
 
+// Flat-vector launchers: P64, P32 or P16 storage (n complex numbers per
+// right-hand side); any other precision code is refused.
+#define WCL_BY_PREC(CALL)                                 \
+    do {                                                  \
+        if (prec == P64) {                                \
+            using T = double;                             \
+            CALL;                                         \
+        } else if (prec == P32) {                         \
+            using T = float;                              \
+            CALL;                                         \
+        } else if (prec == P16) {                         \
+            using T = __half;                             \
+            CALL;                                         \
+        } else {                                          \
+            return hipErrorInvalidValue;                  \
+        }                                                 \
+    } while (0)
+#define WCL_V(x) ((typename CT<T>::V *)(x))
+#define WCL_CV(x) ((const typename CT<T>::V *)(x))
+
 hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
                          hipStream_t st, int nrhs, size_t stride)
 {
-    if (prec == P64)
-        k_bicg_p<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const double2 *)r, (double2 *)p,
-                                                            (const double2 *)v, sc);
-    else
-        k_bicg_p<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const float2 *)r, (float2 *)p,
-                                                           (const float2 *)v, sc);
+    WCL_BY_PREC((k_bicg_p<T><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, WCL_CV(r), WCL_V(p), WCL_CV(v), sc)));
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void *s, const Scalars *sc,
                          hipStream_t st, int nrhs, size_t stride)
 {
-    if (prec == P64)
-        k_bicg_s<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const double2 *)r, (const double2 *)v,
-                                                            (double2 *)s, sc);
-    else
-        k_bicg_s<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (const float2 *)r, (const float2 *)v,
-                                                           (float2 *)s, sc);
+    WCL_BY_PREC((k_bicg_s<T><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, WCL_CV(r), WCL_CV(v), WCL_V(s), sc)));
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r, const void *s,
                           const void *t, const Scalars *sc, hipStream_t st, int nrhs, size_t stride)
 {
-    if (prec == P64)
-        k_bicg_xr<double><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (double2 *)x, (const double2 *)ph,
-                                                             (const double2 *)sh, (double2 *)r, (const double2 *)s,
-                                                             (const double2 *)t, sc);
-    else
-        k_bicg_xr<float><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, (float2 *)x, (const float2 *)ph,
-                                                            (const float2 *)sh, (float2 *)r, (const float2 *)s,
-                                                            (const float2 *)t, sc);
+    WCL_BY_PREC((k_bicg_xr<T><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, WCL_V(x), WCL_CV(ph), WCL_CV(sh),
+                                                                   WCL_V(r), WCL_CV(s), WCL_CV(t), sc)));
     return hipGetLastError();
 }
 
@@ -1139,8 +1160,9 @@ __global__ void __launch_bounds__(256) k_axpby(size_t n, double ar, double ai, c
                                               double bi, typename CT<T>::V *y)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const auto xv = x[i], yv = y[i];
-        y[i] = {(T)(ar * xv.x - ai * xv.y + br * yv.x - bi * yv.y), (T)(ar * xv.y + ai * xv.x + br * yv.y + bi * yv.x)};
+        using C = typename CT<T>::C;
+        const auto xv = ldv(x[i]), yv = ldv(y[i]);
+        stv(y[i], (C)(ar * xv.x - ai * xv.y + br * yv.x - bi * yv.y), (C)(ar * xv.y + ai * xv.x + br * yv.y + bi * yv.x));
     }
 }
 
@@ -1155,31 +1177,29 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_zero(size_t n, typename CT<T>::V *y)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] = {(T)0, (T)0};
+        stv(y[i], (typename CT<T>::C)0, (typename CT<T>::C)0);
 }
 
 hipError_t launch_axpby(int prec, size_t n, double2 a, const void *x, double2 b, void *y, hipStream_t st)
 {
-    if (prec == P64)
-        k_axpby<double><<<blas_grid(n), 256, 0, st>>>(n, a.x, a.y, (const double2 *)x, b.x, b.y, (double2 *)y);
-    else
-        k_axpby<float><<<blas_grid(n), 256, 0, st>>>(n, a.x, a.y, (const float2 *)x, b.x, b.y, (float2 *)y);
+    WCL_BY_PREC((k_axpby<T><<<blas_grid(n), 256, 0, st>>>(n, a.x, a.y, WCL_CV(x), b.x, b.y, WCL_V(y))));
     return hipGetLastError();
 }
 
 hipError_t launch_copy(int prec, size_t n, const void *x, void *y, hipStream_t st)
 {
-    if (prec == P64) k_copy<double><<<blas_grid(n), 256, 0, st>>>(n, (const double2 *)x, (double2 *)y);
-    else k_copy<float><<<blas_grid(n), 256, 0, st>>>(n, (const float2 *)x, (float2 *)y);
+    WCL_BY_PREC((k_copy<T><<<blas_grid(n), 256, 0, st>>>(n, WCL_CV(x), WCL_V(y))));
     return hipGetLastError();
 }
 
 hipError_t launch_zero(int prec, size_t n, void *y, hipStream_t st)
 {
-    if (prec == P64) k_zero<double><<<blas_grid(n), 256, 0, st>>>(n, (double2 *)y);
-    else k_zero<float><<<blas_grid(n), 256, 0, st>>>(n, (float2 *)y);
+    WCL_BY_PREC((k_zero<T><<<blas_grid(n), 256, 0, st>>>(n, WCL_V(y))));
     return hipGetLastError();
 }
+#undef WCL_BY_PREC
+#undef WCL_V
+#undef WCL_CV
 
 }  // namespace wcl
 

@@ -22,8 +22,8 @@ namespace wcl {
 struct RasArgs {
     Geom g;
     int overlap, iters;
-    const float4 *in;   // even field, float4 [6][Vh]
-    float4 *out;
+    const void *in;     // even field (FP32 or FP16 storage, per the SV parameter)
+    void *out;
     const void *links;
     const void *clov_inv;
     float kappa2;
@@ -219,8 +219,9 @@ WCL_D void block_allreduce(double v[NV], double *red)
 
 // JAC: block Jacobi steps (alpha = 1, no reductions) instead of minimal
 // residual; a template parameter so that the minimal-residual kernel keeps
-// its registers.
-template <typename SL, int MAXNE, bool JAC>
+// its registers.  SV: storage of the input and output vectors (float or
+// __half); the block vectors in LDS and all arithmetic stay FP32.
+template <typename SL, int MAXNE, bool JAC, typename SV>
 __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 {
     // workgroup id = tile * nrhs + rhs (the right-hand sides of one tile share
@@ -229,8 +230,8 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     const int rhs = lin % a.nrhs;
     const int blk = lin / a.nrhs;
     if (a.sc && a.sc[rhs].done) return;
-    const float4 *rin = (const float4 *)((const char *)a.in + rhs * a.stride);
-    float4 *rout = (float4 *)((char *)a.out + rhs * a.stride);
+    const char *rin = (const char *)a.in + rhs * a.stride;
+    char *rout = (char *)a.out + rhs * a.stride;
     // component-major with the compile-time stride MAXNE (immediate LDS offsets)
     __shared__ float2 sE[12 * MAXNE];   // MR residual r on the even block sites
     __shared__ float2 sO[12 * MAXNE];   // y = A_oo^-1 H_oe r on the odd block sites
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     // r = the input on the even block sites (zero start: z = 0, r = rhs)
     if (active) {
         cplx<float> r[12];
-        load_spinor<float, float>(rin, SE.g, Vh, r);
+        load_spinor<SV, float>(rin, SE.g, Vh, r);
 #pragma unroll
         for (int c = 0; c < 12; c++) sE[c * MAXNE + t] = make_float2(r[c].re, r[c].im);
     }
@@ -367,7 +368,17 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
         if constexpr (!JAC) {
             // minimal residual: alpha = <q, r> / <q, q> over the block
             block_allreduce<3>(dots, red);
-            if (dots[2] == 0.0) break;
+            if (dots[2] == 0.0) {
+                // the block's residual is zero: its solution stands; on the first
+                // step nothing has been stored yet, and the solution is zero
+                if (it == 0 && active && core) {
+                    cplx<float> z0[12];
+#pragma unroll
+                    for (int c = 0; c < 12; c++) z0[c] = {0.f, 0.f};
+                    store_spinor<SV, float>(rout, SE.g, Vh, z0);
+                }
+                break;
+            }
             ar = (float)(dots[0] / dots[2]);
             ai = (float)(dots[1] / dots[2]);
         }
@@ -379,7 +390,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
 #pragma unroll
                     for (int c = 0; c < 12; c++) z[c] = {0.f, 0.f};
                 } else {
-                    load_spinor<float, float>(rout, SE.g, Vh, z);
+                    load_spinor<SV, float>(rout, SE.g, Vh, z);
                 }
             }
 #pragma unroll
@@ -388,7 +399,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
                 if (core) z[c] = {z[c].re + ar * r.x - ai * r.y, z[c].im + ar * r.y + ai * r.x};
                 sE[c * MAXNE + t] = make_float2(r.x - (ar * qv[c].re - ai * qv[c].im), r.y - (ar * qv[c].im + ai * qv[c].re));
             }
-            if (core) store_spinor<float, float>(rout, SE.g, Vh, z);
+            if (core) store_spinor<SV, float>(rout, SE.g, Vh, z);
         }
     }
 }
@@ -401,14 +412,23 @@ int ras_threads(const Geom &g, int overlap)
     return ((n + 63) / 64) * 64;
 }
 
+// FP16 vectors go with the FP16 links and clover only.
 template <int MAXNE, bool JAC>
 hipError_t ras_dispatch(const RasLaunch &L, const RasArgs &a, dim3 grid, dim3 block, hipStream_t st)
 {
+    if (L.vec_prec == P16) {
+        switch (L.link_prec) {
+            case P16: k_ras<__half, MAXNE, JAC, __half><<<grid, block, 0, st>>>(a); break;
+            case P16C: k_ras<R12h, MAXNE, JAC, __half><<<grid, block, 0, st>>>(a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (L.link_prec) {
-        case P32: k_ras<float, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
-        case P16: k_ras<__half, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
-        case P32C: k_ras<R12f, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
-        case P16C: k_ras<R12h, MAXNE, JAC><<<grid, block, 0, st>>>(a); break;
+        case P32: k_ras<float, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
+        case P16: k_ras<__half, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
+        case P32C: k_ras<R12f, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
+        case P16C: k_ras<R12h, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -419,7 +439,9 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     const Geom &g = *L.g;
     // several right-hand sides need a stride of at least one even field
     if (L.nrhs < 1 || L.nrhs > 4096) return hipErrorInvalidValue;
-    if (L.nrhs > 1 && L.stride < spinor_bytes(4, (size_t)g.Vh)) return hipErrorInvalidValue;
+    const int vp = L.vec_prec ? L.vec_prec : P32;
+    if (vp != P32 && vp != P16) return hipErrorInvalidValue;
+    if (L.nrhs > 1 && L.stride < spinor_bytes(prec_bytes(vp), (size_t)g.Vh)) return hipErrorInvalidValue;
     for (int mu = 0; mu < 4; mu++)
         if (L.overlap > g.B[mu] || g.L[mu] < g.B[mu] + 2 * L.overlap) return hipErrorInvalidValue;
     int ne = 1;
@@ -429,8 +451,8 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.g = g;
     a.overlap = L.overlap;
     a.iters = L.iters;
-    a.in = (const float4 *)L.in;
-    a.out = (float4 *)L.out;
+    a.in = L.in;
+    a.out = L.out;
     a.links = L.links;
     a.clov_inv = L.clov_inv;
     a.kappa2 = L.kappa2;
@@ -462,7 +484,8 @@ void ras_work(const RasLaunch &L, double *bytes, double *flops)
     const double lb = L.link_prec == P32 ? 72.0 : L.link_prec == P16 ? 36.0 : L.link_prec == P32C ? 48.0 : 24.0;
     const double cb = (L.link_prec == P32 || L.link_prec == P32C) ? 288.0 : 144.0;
     const double nr = L.nrhs > 0 ? L.nrhs : 1;
-    *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + nr * 2.0 * 96.0);
+    const double vb = L.vec_prec == P16 ? 48.0 : 96.0;
+    *bytes = (double)g.Vh * (8.0 * lb + 2.0 * cb + nr * 2.0 * vb);
     int e[4];
     double ext = 1.0;
     for (int mu = 0; mu < 4; mu++) {

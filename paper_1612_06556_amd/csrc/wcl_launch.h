@@ -149,8 +149,8 @@ struct RasLaunch {
     int overlap;
     int iters;
     int link_prec;
-    const void *in;      // FP32 even field
-    void *out;           // FP32 even field
+    const void *in;      // even field, FP32 (or FP16 when vec_prec == P16)
+    void *out;           // even field, same storage
     const void *links;
     const void *clov_inv;
     float kappa2;
@@ -158,6 +158,7 @@ struct RasLaunch {
     int nrhs;            // right-hand sides, fields `stride` bytes apart
     size_t stride;
     bool jacobi;         // block solver: false = minimal residual, true = z += r, r -= Dhat_B r
+    int vec_prec;        // storage of in / out: 0 or P32, or P16 (with FP16 links and clover)
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 

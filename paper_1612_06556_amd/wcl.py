@@ -36,7 +36,7 @@ class wcl_solve_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("outer", ctypes.c_int), ("use_ras", ctypes.c_int),
                 ("ras_overlap", ctypes.c_int), ("ras_iters", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int),
-                ("ras_solver", ctypes.c_int)]
+                ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int)]
 
 
 class wcl_solve_info(ctypes.Structure):

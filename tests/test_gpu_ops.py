@@ -178,3 +178,28 @@ def test_stream_ceiling_entry_point():
     assert r > 0 and c > 0
     with pytest.raises(wcl.WclError):
         wcl.wcl_bench_stream(lat.h, 0.5, 3)
+
+
+@pytest.mark.parametrize("prec", [32, 16])
+def test_ras_zero_blocks(prec):
+    """Blocks whose input is zero return zero (regression: their output was
+    left as the previous call's).  First a dense input fills the output, then
+    an input supported in one core only is compared with the oracle."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    lat.set_ras(1, 4, 0)
+    dense = synth.gaussian_spinor(dims, 71)
+    dense[~even_mask(dims)] = 0
+    lat.apply_op(wcl.OP_RAS, to_gpu(dense), prec=prec)
+    n = np.arange(int(np.prod(dims)))
+    x = np.stack([n % 8, (n // 8) % 8, (n // 64) % 8, n // 512], axis=1)
+    v = synth.gaussian_spinor(dims, 72)
+    v[~(np.all(x < 4, axis=1) & even_mask(dims))] = 0
+    out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(v), prec=prec))
+    ref = orc.ras(v, (4, 4, 4, 4), 1, 4)
+    e = rel(out, ref)
+    print(f"ras zero blocks prec={prec} rel={e:.3e}", flush=True)
+    assert e <= (1e-5 if prec == 32 else 3e-3)
+    # cores at t = 8..11: their extended blocks (t = 7..12) miss the support
+    assert np.abs(out[(x[:, 3] >= 8) & (x[:, 3] < 12)]).max() == 0.0

@@ -295,3 +295,32 @@ def test_batch_rhs_per_thread(inner_prec, use_ras):
             assert rel(xs[j][k], xs[0][k]) <= 1e-8
     with pytest.raises(wcl.WclError):
         wcl.wcl_set_batch_tuning(lat.h, 3)
+
+
+@pytest.mark.parametrize("use_ras,compress", [(1, 0), (0, 0), (1, 1), (0, 1)])
+def test_fp16_inner_vectors(use_ras, compress):
+    """FP16 storage of the inner solver's vectors (with FP16 links and clover,
+    FP32 arithmetic): the FP64 outer solver still reaches the oracle's
+    solution; 3 right-hand sides batched."""
+    import torch
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    U = synth.su3_field(dims, 61)
+    lat = wcl.Lattice(dims, -1, (4, 4, 4, 4))
+    lat.set_compression(compress)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    lat.set_params(0.124, 1.0)
+    orc = oracle.Oracle(dims, -1, 0.124, 1.0, U)
+    b = synth.gaussian_spinor(dims, 62, nrhs=3)
+    x, infos, rc = lat.solve(to_gpu(b), tol=1e-10, inner_prec=16, inner_vec_prec=16, use_ras=use_ras,
+                             inner_tol=1e-1)
+    x = to_host(x)
+    print(f"fp16 vectors ras={use_ras} compress={compress}", infos[0], flush=True)
+    assert rc == 0
+    for k in range(3):
+        assert _oracle_residual(orc, x[k], b[k]) <= 1e-10
+        xr, _ = orc.bicgstab_eo(b[k], 1e-13, 20000)
+        assert rel(x[k], xr) <= 1e-8
+    with pytest.raises(wcl.WclError):
+        lat.solve(to_gpu(b[0]), inner_prec=32, inner_vec_prec=16)
+    lat.close()
