@@ -189,6 +189,8 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                 ("mixed_noras_fp32_graph", dict(opts, use_ras=0, use_graph=1), 1),
                 ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16), 1),
                 ("mixed_noras_fp16_graph", dict(opts, use_ras=0, inner_prec=16, use_graph=1), 1),
+                ("mixed_ras_fp16_vec16", dict(opts, inner_prec=16, inner_vec_prec=16), 1),
+                ("mixed_noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16), 1),
                 ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000), 0))
     for name, kw, comp in variants:
         lat.set_compression(comp)
@@ -250,6 +252,7 @@ def sweep(opts, torch, synth, wcl):
         row = {"kappa": kappa, "hop_fp32_r12_cold": _rate(ms, vh, 1320, 8 * 48 + 192)}
         for name, kw in (("mixed_ras_fp32", dict(opts, outer=wcl.OUTER_FBICGSTAB)),
                          ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
+                         ("mixed_noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16)),
                          ("plain_fp64_eo", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64_EO, max_outer=20000)),
                          ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):
             row[name] = _timed_solve(lat, b, torch, **kw)
@@ -299,7 +302,9 @@ def sweep(opts, torch, synth, wcl):
     lat.set_params(KAPPA, CSW)
     wcl.wcl_autotune_hop(lat.h, 16, 2)
     batch = {}
-    for name, kw in (("ras_fp16", dict(opts, inner_prec=16)), ("noras_fp16", dict(opts, use_ras=0, inner_prec=16))):
+    for name, kw in (("ras_fp16", dict(opts, inner_prec=16)), ("noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
+                     ("ras_fp16_vec16", dict(opts, inner_prec=16, inner_vec_prec=16)),
+                     ("noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16))):
         r12 = _timed_solve(lat, b, torch, runs=1, **kw)
         wcl.wcl_set_batch_tuning(lat.h, 4)
         r12r = _timed_solve(lat, b, torch, runs=1, **kw)
