@@ -209,7 +209,40 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     for k in sol:
         sol[k]["speedup_vs_plain_fp64"] = round(base / sol[k]["ms"], 2)
     out["time_to_solution"] = sol
+    out["differentiation_16x16x16x32"] = backward_timing(torch, synth, wcl)
     return out
+
+
+def backward_timing(torch, synth, wcl):
+    """The differentiation workload: L = Re<eta, D^-1 b> at 16^3x32 (kappa
+    0.125), one forward solve and one backward (adjoint solve + link and
+    kappa gradient kernels) through the autograd Function; median of 3."""
+    from paper_1612_06556_amd import autograd
+    dims = (16, 16, 16, 32)
+    U = torch.from_numpy(synth.su3_field(dims, 1005)).cuda()
+    b = torch.from_numpy(synth.gaussian_spinor(dims, 2005)).cuda()
+    eta = torch.from_numpy(synth.gaussian_spinor(dims, 3005)).cuda().reshape(-1)
+    lat = wcl.Lattice(dims, -1)
+    fw, bw = [], []
+    for i in range(4):
+        tU = U.clone().requires_grad_(True)
+        tk = torch.tensor(0.125, dtype=torch.float64, requires_grad=True)
+        tb = b.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = autograd.solve(tU, tk, tb, lat, CSW, tol=1e-10, inner_tol=1e-1)
+        loss = torch.real(torch.vdot(eta, x.reshape(-1)))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if i:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    lat.close()
+    return {"forward_ms": round(float(np.median(fw)) * 1e3, 2), "backward_ms": round(float(np.median(bw)) * 1e3, 2),
+            "note": "backward = adjoint solve + gradient kernels (links, kappa); gradients checked in tests"}
 
 
 def _timed_solve(lat, b, torch, runs=3, **kw):
