@@ -37,13 +37,13 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 
 # Traffic of the RAS kernel from rocprofv3 counters over the bench step:
 # FETCH_SIZE and WRITE_SIZE per working dispatch (KiB), each scaled by what it
-# reads for a 1 GiB device copy (FETCH 524309.3 KiB -> x2.0, WRITE x1.0).
+# reads for a 1 GiB device copy (FETCH 524308.1 KiB -> x2.0, WRITE x1.0).
 # FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
-    "ras": {"fetch_kib": 2138987.8, "fetch_scale": 1048576 / 524309.3125, "write_kib": 82944.2,
+    "ras": {"fetch_kib": 2157932.9, "fetch_scale": 1048576 / 524308.125, "write_kib": 82944.4,
             "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h"),
-            "sha256": "92f401db88d83f38935ca0c09435278b910114fb3818d114a16b6a426c93a493",
+            "sha256": "857c6584b4ed80717626299d621c55c56d1682b8d6bce2cc3aebaf1b8dd4b64c",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
