@@ -64,6 +64,8 @@ def _load():
         getattr(lib, name).argtypes = [ctypes.c_void_p, _dp]
     lib.wco_ras.argtypes = [ctypes.c_void_p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.wco_ras.restype = ctypes.c_int
+    lib.wco_sap.argtypes = [ctypes.c_void_p, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.wco_sap.restype = ctypes.c_int
     for name in ("wco_bicgstab_full", "wco_bicgstab_eo"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp]
@@ -201,6 +203,15 @@ class Oracle:
         rc = self._lib.wco_ras(self._h, _ivec(block), int(overlap), int(iters), int(solver), _p(a), _p(out))
         if rc != 0:
             raise ValueError("oracle RAS: block shape does not fit the lattice")
+        return out
+
+    def sap(self, v, block=(4, 4, 4, 4), overlap: int = 1, iters: int = 4, solver: int = 0):
+        """One multiplicative Schwarz application (16 colours in turn)."""
+        a = self._spinor(v)
+        out = np.empty_like(a)
+        rc = self._lib.wco_sap(self._h, _ivec(block), int(overlap), int(iters), int(solver), _p(a), _p(out))
+        if rc != 0:
+            raise ValueError("oracle SAP: block shape does not fit the lattice")
         return out
 
     # --- solvers ------------------------------------------------------------

@@ -759,17 +759,13 @@ static void block_schur(const wco_ctx *c, const blockmap *B, const cplx *x, cplx
     block_mask(c, B, out, 0);
 }
 
-int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
-            const double *in, double *out)
+/* The restricted block solves of one Schwarz application on the blocks of
+ * one colour (colour < 0: every block).  Colour of a block = the parities of
+ * its block coordinates, bit mu for direction mu (16 colours).  The restricted
+ * result (even core sites) is added to out. */
+static int ras_blocks(const wco_ctx *c, const int block[4], int overlap, int iters, int solver, int colour,
+                      const cplx *vin, cplx *vout)
 {
-    if (solver != 0 && solver != 1) return -1;
-    for (int mu = 0; mu < 4; mu++) {
-        if (block[mu] < 2 || (block[mu] & 1) || c->L[mu] % block[mu]) return -1;
-        if (c->L[mu] < block[mu] + 2 * overlap || overlap < 0) return -1;
-    }
-    const cplx *vin = (const cplx *)in;
-    cplx *vout = (cplx *)out;
-    memset(vout, 0, sizeof(cplx) * 12 * c->V);
     int nb_[4];
     for (int mu = 0; mu < 4; mu++) nb_[mu] = c->L[mu] / block[mu];
     const long nblocks = (long)nb_[0] * nb_[1] * nb_[2] * nb_[3];
@@ -777,13 +773,16 @@ int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int so
 #pragma omp parallel for schedule(dynamic)
     for (long bi = 0; bi < nblocks; bi++) {
         blockmap B;
-        int bo[4];
+        int bo[4], col = 0;
         long rem = bi;
         for (int mu = 0; mu < 4; mu++) {
-            bo[mu] = (int)(rem % nb_[mu]) * block[mu];
+            const int bk = (int)(rem % nb_[mu]);
+            bo[mu] = bk * block[mu];
+            col |= (bk & 1) << mu;
             rem /= nb_[mu];
             B.e[mu] = block[mu] + 2 * overlap;
         }
+        if (colour >= 0 && col != colour) continue;
         B.Ne = (long)B.e[0] * B.e[1] * B.e[2] * B.e[3];
         B.g = malloc(sizeof(long) * B.Ne);
         for (long l = 0; l < B.Ne; l++) {
@@ -810,7 +809,7 @@ int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int so
             }
             for (long i = 0; i < N; i++) { z[i] += alpha * r[i]; r[i] -= alpha * q[i]; }
         }
-        /* restriction: keep the even core sites */
+        /* restriction: keep the even core sites (cores never overlap) */
         for (long l = 0; l < B.Ne; l++) {
             int a[4];
             lcoords(&B, l, a);
@@ -818,10 +817,53 @@ int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int so
             for (int mu = 0; mu < 4; mu++)
                 if (a[mu] < overlap || a[mu] >= overlap + block[mu]) core = 0;
             if (!core || parity(c, B.g[l]) != 0) continue;
-            for (int i = 0; i < 12; i++) vout[B.g[l] * 12 + i] = z[l * 12 + i];
+            for (int i = 0; i < 12; i++) vout[B.g[l] * 12 + i] += z[l * 12 + i];
         }
         free(r); free(z); free(q); free(t1); free(t2); free(B.g);
     }
+    return 0;
+}
+
+static int ras_args_ok(const wco_ctx *c, const int block[4], int overlap, int solver)
+{
+    if (solver != 0 && solver != 1) return 0;
+    for (int mu = 0; mu < 4; mu++) {
+        if (block[mu] < 2 || (block[mu] & 1) || c->L[mu] % block[mu]) return 0;
+        if (c->L[mu] < block[mu] + 2 * overlap || overlap < 0) return 0;
+    }
+    return 1;
+}
+
+int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
+            const double *in, double *out)
+{
+    if (!ras_args_ok(c, block, overlap, solver)) return -1;
+    memset(out, 0, sizeof(cplx) * 12 * c->V);
+    return ras_blocks(c, block, overlap, iters, solver, -1, (const cplx *)in, (cplx *)out);
+}
+
+/* Multiplicative Schwarz: the 16 block colours in turn, each solving on the
+ * residual that the previous colours left:  z = 0;  for colour k:
+ * r = v - Dhat z,  z += (restricted block solves of colour k on r). */
+int wco_sap(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
+            const double *in, double *out)
+{
+    if (!ras_args_ok(c, block, overlap, solver)) return -1;
+    const long N = 12 * c->V;
+    const cplx *v = (const cplx *)in;
+    cplx *z = (cplx *)out, *r = vnew(c), *t = vnew(c);
+    memset(z, 0, sizeof(cplx) * N);
+    for (int k = 0; k < 16; k++) {
+        if (k == 0) {
+            memcpy(r, v, sizeof(cplx) * N);
+        } else {
+            schur_plain(c, z, t);
+            for (long i = 0; i < N; i++) r[i] = v[i] - t[i];
+        }
+        mask_parity(c, r, 0);
+        ras_blocks(c, block, overlap, iters, solver, k, r, z);
+    }
+    free(r); free(t);
     return 0;
 }
 

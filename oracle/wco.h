@@ -63,6 +63,11 @@ void wco_reconstruct(const wco_ctx *c, const double *b, const double *xe, double
  * Jacobi (Richardson) steps z <- z + (r_B - Dhat_B z) from z = 0. */
 int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
             const double *in, double *out);
+/* Multiplicative Schwarz on even vectors: the 16 block colours (parities of
+ * the block coordinates) in turn, each on the residual v - Dhat z left by the
+ * previous colours, same block solver and restriction as wco_ras. */
+int wco_sap(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
+            const double *in, double *out);
 
 /* Solvers; return 0 on convergence, 1 if max iterations hit, 2 on breakdown.
  * iters_out / relres_out receive the iteration count and the final true
