@@ -107,13 +107,16 @@ enum { WCL_OP_HOP = 0, WCL_OP_CLOVER = 1, WCL_OP_CLOVER_INV = 2, WCL_OP_SCHUR = 
        WCL_OP_SCHUR_RHS = 4, WCL_OP_RAS = 5, WCL_OP_D = 6, WCL_OP_DDAG = 7 };
 int wcl_apply_op(wcl_ctx *ctx, int op, const double *in_dev, double *out_dev, int nrhs, int prec);
 /* Schwarz settings of WCL_OP_RAS (a solve sets them from its options):
- * overlap (extension of the cores on every side), iters (block steps) and
- * the block solver: WCL_RAS_MR, minimal residual from zero (the default),
- * or WCL_RAS_JACOBI, the linear alternative z <- z + (r_B - Dhat_B z)
- * (the paper leaves the block solver open, Sec. 2).  WCL_EINVAL when the
+ * overlap (extension of the cores on every side), iters (block steps), the
+ * block solver -- WCL_RAS_MR, minimal residual from zero (the default), or
+ * WCL_RAS_JACOBI, the linear alternative z <- z + (r_B - Dhat_B z) -- and the
+ * scheme: multiplicative = 0 is the additive (restricted) Schwarz of the
+ * paper; 1 runs the 16 block colours (parities of the block coordinates) in
+ * turn, each on the residual in - Dhat z left by the colours before it (the
+ * paper leaves the Schwarz variant open, Sec. 2).  WCL_EINVAL when the
  * extended block does not fit the lattice or one workgroup. */
 enum { WCL_RAS_MR = 0, WCL_RAS_JACOBI = 1 };
-int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters, int solver);
+int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters, int solver, int multiplicative);
 
 /* Solver options. */
 /* FBICGSTAB: FP64 flexible BiCGStab on the even/odd system, preconditioned
@@ -137,6 +140,7 @@ typedef struct {
     int ras_solver;      /* WCL_RAS_MR or WCL_RAS_JACOBI (block solver of the RAS)   */
     int inner_vec_prec;  /* 32, or 16: the inner solver's vectors stored in FP16 (FP32
                           * arithmetic; needs inner_prec 16)                        */
+    int ras_mult;        /* 1: multiplicative Schwarz (colour sweeps), see wcl_set_ras */
 } wcl_solve_opts;
 
 typedef struct {

@@ -63,6 +63,7 @@ struct wcl_ctx {
     double kappa = 0, csw = 0;
     bool have_gauge = false, have_params = false;
     int ras_overlap = 1, ras_iters = 4, ras_solver = WCL_RAS_MR;
+    int ras_mult = 0;   // 1: multiplicative Schwarz (colour sweeps) instead of additive
     std::vector<Buf> ws;        // workspace, indexed by slot
     double *partials = nullptr; // [cap][6][RED_BLOCKS]
     Scalars *sc = nullptr;      // [3][cap]: outer, inner, final/scratch scalars per right-hand side
@@ -209,6 +210,34 @@ int run_ras(wcl_ctx *c, const RasLaunch &R)
     return profiled(c, WCL_K_RAS, b, f, [&] { return launch_ras(R, c->st); });
 }
 
+int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc,
+          int nrhs = 1);
+
+// Multiplicative Schwarz: out = 0; for colour k = 0 .. 15: r = in - Dhat out
+// (r = in for k = 0), then the colour-k block solves of r added to out.  R
+// carries the block recipe, precisions, scalars and right-hand sides; rt, tt
+// and to are vectors of R's storage (residual, Dhat out, Schur odd temp).
+int run_sap(wcl_ctx *c, RasLaunch R, int lprec, int vprec, const void *in, void *out, void *rt, void *tt,
+            void *to)
+{
+    const size_t m = 12 * (size_t)c->Vh;
+    HIPCHK(launch_zero(vprec, R.nrhs * m, out, c->st));
+    R.out = out;
+    R.accumulate = true;
+    for (int k = 0; k < 16; k++) {
+        R.in = in;
+        if (k > 0) {
+            CHK(schur(c, lprec, vprec, out, tt, to, R.sc, R.nrhs));
+            HIPCHK(launch_copy(vprec, R.nrhs * m, in, rt, c->st));
+            HIPCHK(launch_axpby(vprec, R.nrhs * m, make_double2(-1.0, 0.0), tt, make_double2(1.0, 0.0), rt, c->st));
+            R.in = rt;
+        }
+        R.colour = k + 1;
+        CHK(run_ras(c, R));
+    }
+    return WCL_OK;
+}
+
 int run_clover(wcl_ctx *c, int lp, int sp, int p, const void *clov, const void *in, void *out, int nrhs = 1,
                size_t in_stride = 0, size_t out_stride = 0)
 {
@@ -254,7 +283,7 @@ int full_D(wcl_ctx *c, int lprec, int sprec, const void *in, void *out, int dagg
 
 // Schur operator on even fields: tmp_o = A_oo^-1 H_oe in_e ; out_e = in_e - k^2 A_ee^-1 H_eo tmp_o
 int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc,
-          int nrhs = 1)
+          int nrhs)
 {
     HopLaunch L = hop_base(c, lprec, sprec);
     L.clov = clovinv_for(c, lprec);
@@ -388,6 +417,8 @@ enum Slot {
     S_GX, S_GY, S_GK, S_GG, S_GHX, S_GCX,
     // SU(3) check partials
     S_SU3,
+    // multiplicative Schwarz: residual, Dhat z, Schur odd temporary
+    S_SAPR, S_SAPT, S_SAPO,
     // bench copies start here
     S_BENCH = 64,
 };
@@ -574,8 +605,9 @@ int wcl_set_params(wcl_ctx *c, double kappa, double csw)
     return WCL_OK;
 }
 
-int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver)
+int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver, int multiplicative)
 {
+    if (c && multiplicative != 0 && multiplicative != 1) return fail(WCL_EINVAL, "multiplicative must be 0 or 1");
     if (!c) return fail(WCL_EINVAL, "null context");
     if (overlap < 0 || iters < 1) return fail(WCL_EINVAL, "overlap >= 0 and iters >= 1 required");
     if (solver != WCL_RAS_MR && solver != WCL_RAS_JACOBI) return fail(WCL_EINVAL, "unknown RAS block solver");
@@ -586,6 +618,7 @@ int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver)
     c->ras_overlap = overlap;
     c->ras_iters = iters;
     c->ras_solver = solver;
+    c->ras_mult = multiplicative;
     return WCL_OK;
 }
 
@@ -658,7 +691,15 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.sc = nullptr;
             R.nrhs = 1;
             R.stride = 0;
-            CHK(run_ras(c, R));
+            if (c->ras_mult) {
+                void *rt, *tt, *to;
+                CHK(wsget(c, S_SAPR, half_bytes(sp, Vh), &rt));
+                CHK(wsget(c, S_SAPT, half_bytes(sp, Vh), &tt));
+                CHK(wsget(c, S_SAPO, half_bytes(sp, Vh), &to));
+                CHK(run_sap(c, R, lp, sp, R.in, R.out, rt, tt, to));
+            } else {
+                CHK(run_ras(c, R));
+            }
             HIPCHK(launch_zero(P64, 12 * Vh, par(b64, P64, Vh, 1), c->st));
             break;
         }
@@ -695,6 +736,7 @@ void wcl_default_opts(wcl_solve_opts *o)
     o->ras_iters = 4;
     o->ras_solver = WCL_RAS_MR;
     o->inner_vec_prec = 32;
+    o->ras_mult = 0;
     o->inner_prec = 32;
     o->use_graph = 0;
     o->check_every = 8;
@@ -716,6 +758,8 @@ struct SolveWs {
     void *bh, *xe, *r, *rt, *p, *v, *s, *t, *ph, *sh, *o, *o2;
     // FP32 even vectors [n][6][Vh] float4
     void *rhs, *x32, *r32, *rt32, *p32, *v32, *s32, *t32, *ph32, *sh32, *o32;
+    // multiplicative Schwarz temporaries (same storage; null unless used)
+    void *sapr = nullptr, *sapt = nullptr, *sapo = nullptr;
 };
 
 int get_ws(wcl_ctx *c, SolveWs &w, bool inner, bool plain, int n)
@@ -733,6 +777,11 @@ int get_ws(wcl_ctx *c, SolveWs &w, bool inner, bool plain, int n)
     if (inner) {
         void **v32[] = {&w.rhs, &w.x32, &w.r32, &w.rt32, &w.p32, &w.v32, &w.s32, &w.t32, &w.ph32, &w.sh32, &w.o32};
         for (int k = 0; k < 11; k++) CHK(wsget(c, S_RHS32 + k, e32, v32[k]));
+        if (c->ras_mult) {
+            CHK(wsget(c, S_SAPR, e32, &w.sapr));
+            CHK(wsget(c, S_SAPT, e32, &w.sapt));
+            CHK(wsget(c, S_SAPO, e32, &w.sapo));
+        }
     }
     return WCL_OK;
 }
@@ -773,7 +822,8 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         R.vec_prec = vp;
         R.in = w.p32;
         R.out = w.ph32;
-        CHK(run_ras(c, R));
+        if (c->ras_mult) CHK(run_sap(c, R, lp, vp, w.p32, w.ph32, w.sapr, w.sapt, w.sapo));
+        else CHK(run_ras(c, R));
         ph = w.ph32;
     }
     CHK(schur(c, lp, vp, ph, w.v32, w.o32, sc, n));
@@ -786,7 +836,8 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
     if (cfg.ras) {
         R.in = w.s32;
         R.out = w.sh32;
-        CHK(run_ras(c, R));
+        if (c->ras_mult) CHK(run_sap(c, R, lp, vp, w.s32, w.sh32, w.sapr, w.sapt, w.sapo));
+        else CHK(run_ras(c, R));
         sh = w.sh32;
     }
     CHK(schur(c, lp, vp, sh, w.t32, w.o32, sc, n));
@@ -1146,7 +1197,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
     const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
     const bool inner = !plain && !plain_eo;
-    if (o.use_ras && inner) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver));
+    if (o.use_ras && inner) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver, o.ras_mult));
     const int n = nrhs;
     CHK(ensure_batch(c, n));
     SolveWs w;

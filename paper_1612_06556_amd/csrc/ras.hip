@@ -30,6 +30,8 @@ struct RasArgs {
     const Scalars *sc;
     int nrhs;
     size_t stride;   // bytes between right-hand sides
+    int colour;      // 0: every block; k + 1: only the blocks of colour k
+    int accumulate;  // add the restricted result to the output instead of writing it
 };
 
 // global (tile coordinate, in-tile coordinate) of extended-block coordinate a
@@ -251,6 +253,12 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
         bc[2] = r % g.NB[2];
         bc[3] = r / g.NB[2];
     }
+    // colour = parities of the block coordinates (bit mu); a colour sweep of
+    // the multiplicative scheme runs the blocks of one colour only
+    if (a.colour > 0) {
+        const int col = (bc[0] & 1) | ((bc[1] & 1) << 1) | ((bc[2] & 1) << 2) | ((bc[3] & 1) << 3);
+        if (col != a.colour - 1) return;
+    }
 
     for (int i = threadIdx.x; i < 2 * Ne; i += blockDim.x) {
         const int q = i >= Ne ? 1 : 0;
@@ -371,7 +379,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             if (dots[2] == 0.0) {
                 // the block's residual is zero: its solution stands; on the first
                 // step nothing has been stored yet, and the solution is zero
-                if (it == 0 && active && core) {
+                if (it == 0 && active && core && !a.accumulate) {
                     cplx<float> z0[12];
 #pragma unroll
                     for (int c = 0; c < 12; c++) z0[c] = {0.f, 0.f};
@@ -386,7 +394,7 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
             // z += alpha r (kept only where it is written: the core), r -= alpha q
             cplx<float> z[12];
             if (core) {
-                if (it == 0) {
+                if (it == 0 && !a.accumulate) {
 #pragma unroll
                     for (int c = 0; c < 12; c++) z[c] = {0.f, 0.f};
                 } else {
@@ -459,6 +467,9 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.sc = L.sc;
     a.nrhs = L.nrhs;
     a.stride = L.stride;
+    if (L.colour < 0 || L.colour > 16) return hipErrorInvalidValue;
+    a.colour = L.colour;
+    a.accumulate = L.accumulate ? 1 : 0;
     const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
     const int threads = ras_threads(g, L.overlap);
     if (threads > 1024) return hipErrorInvalidValue;
@@ -498,7 +509,13 @@ void ras_work(const RasLaunch &L, double *bytes, double *flops)
     // per iteration: hops, clover on every site, q = r - k^2 w (48 per even site),
     // two dot products (96, minimal residual only) and the z, r updates (96)
     const double per_iter = hops * 168.0 + ext * 504.0 + ne * (48.0 + (L.jacobi ? 0.0 : 96.0) + 96.0);
-    const double nblk = (double)g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
+    double nblk = 1.0;
+    for (int mu = 0; mu < 4; mu++) {
+        if (L.colour > 0) nblk *= ((L.colour - 1) >> mu & 1) ? g.NB[mu] / 2 : (g.NB[mu] + 1) / 2;
+        else nblk *= g.NB[mu];
+    }
+    const double frac = nblk / ((double)g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3]);
+    *bytes *= frac;
     *flops = per_iter * L.iters * nblk * nr;
 }
 

@@ -159,6 +159,9 @@ struct RasLaunch {
     size_t stride;
     bool jacobi;         // block solver: false = minimal residual, true = z += r, r -= Dhat_B r
     int vec_prec;        // storage of in / out: 0 or P32, or P16 (with FP16 links and clover)
+    int colour;          // 0: every block; k + 1: the blocks of colour k only (bit mu = parity of
+                         // the block coordinate in direction mu)
+    bool accumulate;     // add the restricted block results to out (else write them)
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 

@@ -36,7 +36,7 @@ class wcl_solve_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("outer", ctypes.c_int), ("use_ras", ctypes.c_int),
                 ("ras_overlap", ctypes.c_int), ("ras_iters", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int),
-                ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int)]
+                ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int), ("ras_mult", ctypes.c_int)]
 
 
 class wcl_solve_info(ctypes.Structure):
@@ -73,7 +73,7 @@ def load():
     lib.wcl_set_stream.argtypes = [_vp, _vp]
     lib.wcl_set_gauge.argtypes = [_vp, _vp]
     lib.wcl_set_params.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
-    lib.wcl_set_ras.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.wcl_set_ras.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply_op.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int]
     lib.wcl_default_opts.argtypes = [ctypes.POINTER(wcl_solve_opts)]
@@ -131,8 +131,8 @@ def wcl_set_params(h, kappa, csw):
     _check(load().wcl_set_params(h, float(kappa), float(csw)))
 
 
-def wcl_set_ras(h, overlap, iters, solver=0):
-    _check(load().wcl_set_ras(h, int(overlap), int(iters), int(solver)))
+def wcl_set_ras(h, overlap, iters, solver=0, multiplicative=0):
+    _check(load().wcl_set_ras(h, int(overlap), int(iters), int(solver), int(multiplicative)))
 
 
 def wcl_apply(h, in_ptr, out_ptr, nrhs, dagger, prec):
@@ -274,9 +274,10 @@ class Lattice:
         wcl_apply_op(self.h, op, psi.data_ptr(), out.data_ptr(), nrhs, prec)
         return out
 
-    def set_ras(self, overlap=1, iters=4, solver=0):
-        """RAS overlap, block steps and block solver (RAS_MR or RAS_JACOBI)."""
-        wcl_set_ras(self.h, overlap, iters, solver)
+    def set_ras(self, overlap=1, iters=4, solver=0, multiplicative=0):
+        """Schwarz overlap, block steps, block solver (RAS_MR or RAS_JACOBI) and
+        scheme (0 additive, 1 multiplicative colour sweeps)."""
+        wcl_set_ras(self.h, overlap, iters, solver, multiplicative)
 
     def solve(self, b, raise_on_error=True, **kw):
         b, nrhs = self._spinors(b)

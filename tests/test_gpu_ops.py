@@ -104,6 +104,26 @@ def test_ras_variants(overlap, solver, iters):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("prec,overlap,solver", [(32, 1, 0), (16, 1, 0), (32, 0, 1)])
+def test_sap_application(prec, overlap, solver):
+    """Multiplicative Schwarz (16 colour sweeps with residual updates) against
+    the oracle's: FP32 1e-5, FP16 links and clover 3e-3."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    psi = synth.gaussian_spinor(dims, 17)
+    psi[~even_mask(dims)] = 0
+    lat.set_ras(overlap, 4, solver, 1)
+    try:
+        out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=prec))
+    finally:
+        lat.set_ras(1, 4, 0, 0)
+    ref = orc.sap(psi, (4, 4, 4, 4), overlap, 4, solver)
+    e = rel(out, ref)
+    print(f"sap prec={prec} overlap={overlap} solver={solver} rel={e:.3e}", flush=True)
+    assert e <= (1e-5 if prec == 32 else 3e-3)
+
+
 def test_ras_small_cores():
     """2^4 cores with overlap 1 on a 4x4x4x8 lattice (extended block = 4^4)."""
     from paper_1612_06556_amd import wcl

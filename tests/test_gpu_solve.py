@@ -56,20 +56,20 @@ def test_plain_fp64_eo_8x4():
     assert rel(x, _reference(orc, b, "8a")) <= 1e-8
 
 
-@pytest.mark.parametrize("overlap,solver", [(0, 0), (1, 1), (0, 1)])
-def test_schwarz_variants_8x4(overlap, solver):
+@pytest.mark.parametrize("overlap,solver,mult", [(0, 0, 0), (1, 1, 0), (0, 1, 0), (1, 0, 1), (0, 1, 1)])
+def test_schwarz_variants_8x4(overlap, solver, mult):
     """RAS variants inside the mixed solve: no overlap, block Jacobi steps."""
     dims = (8, 8, 8, 8)
     lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
     b = synth.gaussian_spinor(dims, 2001)
-    x, info, rc = lat.solve(to_gpu(b), use_ras=1, ras_overlap=overlap, ras_solver=solver, tol=1e-10,
-                            inner_tol=1e-2, max_outer=200)
+    x, info, rc = lat.solve(to_gpu(b), use_ras=1, ras_overlap=overlap, ras_solver=solver, ras_mult=mult,
+                            tol=1e-10, inner_tol=1e-2, max_outer=200)
     x = to_host(x)
-    print(f"schwarz overlap={overlap} solver={solver}", info, flush=True)
+    print(f"schwarz overlap={overlap} solver={solver} mult={mult}", info, flush=True)
     assert rc == 0 and info["status"] == 0
     assert _oracle_residual(orc, x, b) <= 1e-10
     assert rel(x, _reference(orc, b, "8a")) <= 1e-8
-    lat.set_ras(1, 4, 0)
+    lat.set_ras(1, 4, 0, 0)
 
 
 @pytest.mark.parametrize("outer,use_ras,inner_prec", [(0, 1, 32), (0, 0, 32), (1, 1, 32), (0, 1, 16), (1, 0, 16)])
