@@ -311,6 +311,8 @@ def sweep(opts, torch, synth, wcl):
                      ("jacobi_overlap1_iters4", dict(ras_solver=wcl.RAS_JACOBI)),
                      ("jacobi_overlap0_iters4", dict(ras_solver=wcl.RAS_JACOBI, ras_overlap=0)),
                      ("defect_correction_mr", dict(outer=wcl.OUTER_DC)),
+                     ("multiplicative_mr_overlap1_iters4", dict(ras_mult=1)),
+                     ("multiplicative_mr_overlap0_iters4", dict(ras_mult=1, ras_overlap=0)),
                      ("no_ras", dict(use_ras=0))):
         schwarz[name] = _timed_solve(lat, b, torch, **dict(opts, **kw))
     out["schwarz_24x24x24x32"] = schwarz

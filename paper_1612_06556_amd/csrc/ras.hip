@@ -246,18 +246,23 @@ __global__ void __launch_bounds__(MAXNE == 648 ? 704 : 128) k_ras(RasArgs a)
     const int Ne = (e0 * e1 * e2 * e3) >> 1;
     const int e0h = e0 >> 1;
     int bc[4];
-    {
+    if (a.colour > 0) {
+        // a colour sweep of the multiplicative scheme: the grid holds only the
+        // blocks of that colour (bit mu = parity of the block coordinate)
+        int r = blk;
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            const int bit = ((a.colour - 1) >> mu) & 1;
+            const int cnt = (g.NB[mu] + 1 - bit) >> 1;
+            bc[mu] = 2 * (r % cnt) + bit;
+            r /= cnt;
+        }
+    } else {
         int r = blk;
         bc[0] = r % g.NB[0]; r /= g.NB[0];
         bc[1] = r % g.NB[1]; r /= g.NB[1];
         bc[2] = r % g.NB[2];
         bc[3] = r / g.NB[2];
-    }
-    // colour = parities of the block coordinates (bit mu); a colour sweep of
-    // the multiplicative scheme runs the blocks of one colour only
-    if (a.colour > 0) {
-        const int col = (bc[0] & 1) | ((bc[1] & 1) << 1) | ((bc[2] & 1) << 2) | ((bc[3] & 1) << 3);
-        if (col != a.colour - 1) return;
     }
 
     for (int i = threadIdx.x; i < 2 * Ne; i += blockDim.x) {
@@ -470,7 +475,12 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     if (L.colour < 0 || L.colour > 16) return hipErrorInvalidValue;
     a.colour = L.colour;
     a.accumulate = L.accumulate ? 1 : 0;
-    const int nblk = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
+    int nblk = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        const int bit = L.colour > 0 ? ((L.colour - 1) >> mu) & 1 : 0;
+        nblk *= L.colour > 0 ? (g.NB[mu] + 1 - bit) / 2 : g.NB[mu];
+    }
+    if (nblk == 0) return hipSuccess;   // no block of that colour
     const int threads = ras_threads(g, L.overlap);
     if (threads > 1024) return hipErrorInvalidValue;
     dim3 grid(nblk * a.nrhs), block(threads);
