@@ -210,6 +210,21 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
         sol[k]["speedup_vs_plain_fp64"] = round(base / sol[k]["ms"], 2)
     out["time_to_solution"] = sol
     out["differentiation_16x16x16x32"] = backward_timing(torch, synth, wcl)
+    # setup: gauge ingest + casts + SU(3) check + two-row copies, then clover build and inversion
+    gU = torch.from_numpy(U).cuda()
+    ts_g, ts_p = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.set_gauge(gU)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lat.set_params(KAPPA, CSW)
+        torch.cuda.synchronize()
+        ts_g.append(t2 - t1)
+        ts_p.append(time.perf_counter() - t2)
+    out["setup_ms"] = {"set_gauge": round(float(np.median(ts_g)) * 1e3, 3),
+                       "set_params_clover_build": round(float(np.median(ts_p)) * 1e3, 3)}
     return out
 
 
