@@ -153,6 +153,12 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 1000, 4)), Vh, 1320, 768)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     lat.set_compression(1)
+    # the same launch shape without the LDS staging of input spinors
+    wcl.wcl_set_hop_staging(lat.h, 0)
+    for prec in (32, 16):
+        ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
+        hop[f"fp{prec}_r12_cold_unstaged"] = _rate(ms, Vh, 1320, 8 * (48 if prec == 32 else 24) + 192)
+    wcl.wcl_set_hop_staging(lat.h, 1)
     wcl.wcl_autotune_hop(lat.h, 32, 4)
     out["hop_standalone"] = hop
     out["clover_standalone"] = clov

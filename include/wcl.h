@@ -212,6 +212,13 @@ int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
  * (may be NULL) receives {block, depth, xcd}. */
 int wcl_set_tuning(wcl_ctx *ctx, int hop_block, int hop_depth, int hop_xcd, int hop_nontemporal);
 int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
+/* Staged input of the hopping kernel (default on): each workgroup first
+ * copies the input spinors of its own half-sites into LDS and reads the
+ * neighbours that fall in that range from there (in the blocked layout most
+ * of a tile's hops stay inside the tile), the rest from global memory.
+ * Applies to depth-2, non-dagger, temporal-load launches; results are
+ * bitwise those of the unstaged kernel.  enable = 0 switches it off. */
+int wcl_set_hop_staging(wcl_ctx *ctx, int enable);
 /* Batched launches (nrhs > 1) of the FP32-vector hopping kernels (the inner
  * solver's Schur halves): rhs_per_thread = 1 gives each right-hand side its
  * own workgroups (links shared through L2); 2 or 4 keep that many right-hand

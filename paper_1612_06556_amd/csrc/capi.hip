@@ -70,7 +70,7 @@ struct wcl_ctx {
     Scalars *sc_host = nullptr; // pinned mirror
     int cap = 0;                // right-hand sides the scalar and partial buffers hold
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
-    int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0;
+    int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0, hop_lds = 1;
     int hop_rhs = 1;   // right-hand sides per thread in batched launches (1, 2, 4)
     // event profiling of kernel classes
     struct Rec {
@@ -161,6 +161,7 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     L.depth = c->hop_depth;
     L.rhs_per_thread = c->hop_rhs;
     L.nontemporal = c->hop_nt;
+    L.lds_stage = c->hop_lds;
     return L;
 }
 
@@ -1487,6 +1488,13 @@ extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_
     c->hop_depth = hop_depth;
     c->hop_xcd = hop_xcd ? 1 : 0;
     c->hop_nt = hop_nontemporal ? 1 : 0;
+    return WCL_OK;
+}
+
+extern "C" int wcl_set_hop_staging(wcl_ctx *c, int enable)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    c->hop_lds = enable ? 1 : 0;
     return WCL_OK;
 }
 

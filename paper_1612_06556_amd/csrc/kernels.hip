@@ -454,9 +454,49 @@ WCL_D void pipeline_fence(cplx<R> acc[12], uint32_t &hn, uint32_t &h)
                    "+v"(acc[10].re), "+v"(acc[10].im), "+v"(acc[11].re), "+v"(acc[11].im), "+v"(hn), "+v"(h));
 }
 
-template <typename SL, typename SS, int K, bool NT, typename R>
-WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, HopStage<SL, R> &st,
-                    cplx<R> acc[12])
+// Staged input: a workgroup first copies the input spinors of its own NS
+// consecutive half-sites (its tile, or a part or pair of tiles) into LDS; a
+// neighbour inside that range is then read from LDS, one outside it from
+// global memory.  In the blocked layout most neighbours of a tile lie in it.
+typedef const __attribute__((address_space(3))) u32x4 *lds_u4p;
+struct LdsIn {
+    lds_u4p s;       // uint4 [words][NS]
+    uint32_t base;   // first half index of the tile
+};
+
+// A spinor from the LDS copy of the tile (same word layout as the field).
+template <typename S, int NS, typename R>
+WCL_D void lds_spinor(lds_u4p s, uint32_t l, cplx<R> v[12])
+{
+    if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (uint32_t i = 0; i < 12; i++) {
+            const u32x4 u = s[i * NS + l];
+            v[i] = {(R)__hiloint2double(u.y, u.x), (R)__hiloint2double(u.w, u.z)};
+        }
+    } else if constexpr (sizeof(S) == 4) {
+#pragma unroll
+        for (uint32_t k = 0; k < 6; k++) {
+            const u32x4 u = s[k * NS + l];
+            v[2 * k] = {(R)__uint_as_float(u.x), (R)__uint_as_float(u.y)};
+            v[2 * k + 1] = {(R)__uint_as_float(u.z), (R)__uint_as_float(u.w)};
+        }
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < 3; k++) {
+            const u32x4 u = s[k * NS + l];
+            float2 a = h2f2(u.x), b = h2f2(u.y), c = h2f2(u.z), d = h2f2(u.w);
+            v[4 * k + 0] = {(R)a.x, (R)a.y};
+            v[4 * k + 1] = {(R)b.x, (R)b.y};
+            v[4 * k + 2] = {(R)c.x, (R)c.y};
+            v[4 * k + 3] = {(R)d.x, (R)d.y};
+        }
+    }
+}
+
+template <typename SL, typename SS, int K, bool NT, int NS, typename R>
+WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in, const LdsIn &li,
+                    HopStage<SL, R> &st, cplx<R> acc[12])
 {
     constexpr int MU = K >> 1;
     constexpr bool FWD = (K & 1) == 0;
@@ -465,7 +505,13 @@ WCL_D void hop_load(const HopArgs &a, const Site &s, uint32_t h0, const char *in
     uint32_t hn = (uint32_t)neighbour(g, s, MU, FWD ? +1 : -1);
     uint32_t h = h0;
     pipeline_fence(acc, hn, h);
-    load_spinor<SS, R>(in, hn, Vh, st.psi);
+    if constexpr (NS > 0) {
+        const uint32_t l = hn - li.base;
+        if (l < (uint32_t)NS) lds_spinor<SS, NS, R>(li.s, l, st.psi);
+        else load_spinor<SS, R>(in, hn, Vh, st.psi);
+    } else {
+        load_spinor<SS, R>(in, hn, Vh, st.psi);
+    }
     if (FWD) load_link_raw<SL, NT>(a.links, MU, a.p, h, Vh, st.u);
     else load_link_raw<SL, NT>(a.links, MU, 1 - a.p, hn, Vh, st.u);
     st.sign = R(1);
@@ -489,32 +535,33 @@ WCL_D void hop_compute(const HopStage<SL, R> &st, cplx<R> acc[12])
     accumulate<MU, S, R>(acc, uh);
 }
 
-template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
-WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<SL, R> st[D],
-                        cplx<R> acc[12])
+template <typename SL, typename SS, int SG, int D, int K, bool NT, int NS, typename R>
+WCL_D void hop_prologue(const HopArgs &a, const Site &s, uint32_t h, const char *in, const LdsIn &li,
+                        HopStage<SL, R> st[D], cplx<R> acc[12])
 {
     if constexpr (K < D - 1) {
-        hop_load<SL, SS, K, NT, R>(a, s, h, in, st[K], acc);
-        hop_prologue<SL, SS, SG, D, K + 1, NT, R>(a, s, h, in, st, acc);
+        hop_load<SL, SS, K, NT, NS, R>(a, s, h, in, li, st[K], acc);
+        hop_prologue<SL, SS, SG, D, K + 1, NT, NS, R>(a, s, h, in, li, st, acc);
     }
 }
 
 // hop K is computed while the operands of hop K + D - 1 are in flight
-template <typename SL, typename SS, int SG, int D, int K, bool NT, typename R>
-WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, HopStage<SL, R> st[D],
-                        cplx<R> acc[12])
+template <typename SL, typename SS, int SG, int D, int K, bool NT, int NS, typename R>
+WCL_D void hop_pipeline(const HopArgs &a, const Site &s, uint32_t h, const char *in, const LdsIn &li,
+                        HopStage<SL, R> st[D], cplx<R> acc[12])
 {
     if constexpr (K < 8) {
-        if constexpr (K + D - 1 < 8) hop_load<SL, SS, K + D - 1, NT, R>(a, s, h, in, st[(K + D - 1) % D], acc);
+        if constexpr (K + D - 1 < 8)
+            hop_load<SL, SS, K + D - 1, NT, NS, R>(a, s, h, in, li, st[(K + D - 1) % D], acc);
         hop_compute<K, SG, SL, R>(st[K % D], acc);
-        hop_pipeline<SL, SS, SG, D, K + 1, NT, R>(a, s, h, in, st, acc);
+        hop_pipeline<SL, SS, SG, D, K + 1, NT, NS, R>(a, s, h, in, li, st, acc);
     }
 }
 
 // NT: links and clover loaded non-temporally (a single right-hand side reads
 // them once per launch).  Off by default: repeated applications in a solver
 // find the links in the Infinity Cache only when they were loaded normally.
-template <typename SL, typename SS, int MODE, bool DAG, int DEPTH, bool NT>
+template <typename SL, typename SS, int MODE, bool DAG, int DEPTH, bool NT, int NS>
 __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 {
     using R = typename Real<SL>::T;
@@ -526,9 +573,22 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     const int bid = lin / a.nrhs;
     if (a.sc && a.sc[rhs].done) return;
     const int h = bid * blockDim.x + threadIdx.x;
+    const char *in = (const char *)a.in + rhs * a.in_stride;
+    constexpr int NWORDS = (int)sizeof(SS) * 24 / 16;   // 16-byte words per input spinor
+    __shared__ uint4 sin[NS > 0 ? NWORDS * NS : 1];
+    LdsIn li{(lds_u4p)sin, 0u};
+    if constexpr (NS > 0) {
+        // blockDim.x == NS: thread t stages half-site base + t
+        li.base = (uint32_t)(bid * NS);
+        if (h < a.g.Vh) {
+#pragma unroll
+            for (int k = 0; k < NWORDS; k++)
+                sin[k * NS + threadIdx.x] = ldf<uint4>(in, ((uint32_t)k * (uint32_t)a.g.Vh + (uint32_t)h) * 16u);
+        }
+        __syncthreads();
+    }
     if (h >= a.g.Vh) return;
     const size_t Vh = a.g.Vh;
-    const char *in = (const char *)a.in + rhs * a.in_stride;
     char *out = (char *)a.out + rhs * a.out_stride;
     const Site s = decompose(a.g, h, a.p);
     constexpr int SG = DAG ? -1 : 1;
@@ -536,8 +596,8 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = {R(0), R(0)};
     HopStage<SL, R> st[DEPTH];
-    hop_prologue<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
-    hop_pipeline<SL, SS, SG, DEPTH, 0, NT, R>(a, s, h, in, st, acc);
+    hop_prologue<SL, SS, SG, DEPTH, 0, NT, NS, R>(a, s, h, in, li, st, acc);
+    hop_pipeline<SL, SS, SG, DEPTH, 0, NT, NS, R>(a, s, h, in, li, st, acc);
 
     if constexpr (MODE == HOP) {
         store_spinor<SS, R>(out, h, Vh, acc);
@@ -715,11 +775,16 @@ template <typename SL, typename SS, int MODE>
 static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
 {
     const bool nt = L.nontemporal && a.nrhs == 1;
-    if (L.dagger) k_hop<SL, SS, MODE, true, 2, false><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 3 && nt) k_hop<SL, SS, MODE, false, 3, true><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3, false><<<grid, block, 0, st>>>(a);
-    else if (nt) k_hop<SL, SS, MODE, false, 2, true><<<grid, block, 0, st>>>(a);
-    else k_hop<SL, SS, MODE, false, 2, false><<<grid, block, 0, st>>>(a);
+    // staged input spinors (depth 2, non-dagger): one LDS slot per thread
+    const bool staged = L.lds_stage && !L.dagger && !nt && L.depth == 2;
+    if (staged && block.x == 64) k_hop<SL, SS, MODE, false, 2, false, 64><<<grid, block, 0, st>>>(a);
+    else if (staged && block.x == 128) k_hop<SL, SS, MODE, false, 2, false, 128><<<grid, block, 0, st>>>(a);
+    else if (staged && block.x == 256) k_hop<SL, SS, MODE, false, 2, false, 256><<<grid, block, 0, st>>>(a);
+    else if (L.dagger) k_hop<SL, SS, MODE, true, 2, false, 0><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 3 && nt) k_hop<SL, SS, MODE, false, 3, true, 0><<<grid, block, 0, st>>>(a);
+    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3, false, 0><<<grid, block, 0, st>>>(a);
+    else if (nt) k_hop<SL, SS, MODE, false, 2, true, 0><<<grid, block, 0, st>>>(a);
+    else k_hop<SL, SS, MODE, false, 2, false, 0><<<grid, block, 0, st>>>(a);
 }
 
 template <typename SL, typename SS>

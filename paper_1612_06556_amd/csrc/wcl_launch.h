@@ -42,6 +42,7 @@ struct HopLaunch {
     int block;          // threads per workgroup (64..256)
     int depth;          // hops whose operands are in flight per thread (2, 3)
     int nontemporal;    // links / clover loaded non-temporally (single right-hand side only)
+    int lds_stage;      // 1: stage each 128-site tile's input spinors in LDS (block 128, 4^4 tiles)
     int rhs_per_thread; // 2 or 4: batched launches keep that many right-hand sides per thread
                         // (FP32 spinors, modes HOP / CLOV_H / XPAY); else one per workgroup
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done

@@ -88,6 +88,7 @@ def load():
     lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
+    lib.wcl_set_hop_staging.argtypes = [_vp, ctypes.c_int]
     lib.wcl_set_compression.argtypes = [_vp, ctypes.c_int]
     lib.wcl_set_batch_tuning.argtypes = [_vp, ctypes.c_int]
     lib.wcl_bench_stream.argtypes = [_vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -208,6 +209,10 @@ def wcl_autotune_hop(h, prec, copies):
     best = (ctypes.c_int * 3)()
     _check(load().wcl_autotune_hop(h, int(prec), int(copies), best))
     return {"hop_block": best[0], "hop_depth": best[1], "hop_xcd": best[2]}
+
+
+def wcl_set_hop_staging(h, enable):
+    _check(load().wcl_set_hop_staging(h, int(enable)))
 
 
 # --- convenience wrapper -----------------------------------------------------
