@@ -41,9 +41,9 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 # FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
-    "ras": {"fetch_kib": 2157932.9, "fetch_scale": 1048576 / 524308.125, "write_kib": 82944.4,
+    "ras": {"fetch_kib": 2154751.4, "fetch_scale": 1048576 / 524308.0625, "write_kib": 82944.6,
             "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h"),
-            "sha256": "857c6584b4ed80717626299d621c55c56d1682b8d6bce2cc3aebaf1b8dd4b64c",
+            "sha256": "f10250d667c77bf095ffdbba680876ef323bb9e68cb3b8f79c9d6182363a445a",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
