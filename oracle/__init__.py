@@ -197,7 +197,8 @@ class Oracle:
         return out
 
     def ras(self, v, block=(4, 4, 4, 4), overlap: int = 1, iters: int = 4, solver: int = 0):
-        """One RAS application (solver 0: minimal residual, 1: block Jacobi)."""
+        """One RAS application (solver 0: minimal residual, 1: block Jacobi,
+        2: block BiCGStab)."""
         a = self._spinor(v)
         out = np.empty_like(a)
         rc = self._lib.wco_ras(self._h, _ivec(block), int(overlap), int(iters), int(solver), _p(a), _p(out))

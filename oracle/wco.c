@@ -759,6 +759,42 @@ static void block_schur(const wco_ctx *c, const blockmap *B, const cplx *x, cplx
     block_mask(c, B, out, 0);
 }
 
+/* Block BiCGStab (van der Vorst 1992) on Dhat_B z = r_B from z = 0 with the
+ * shadow residual rh = r_B, `iters` iterations of two block operator
+ * applications each.  The block stops (z as it stands) when rho = <rh, r> or
+ * <rh, v> is exactly zero; <t, t> = 0 means s = 0, and the step ends with
+ * omega = 0.  On entry r = r_B; q, t1, t2 are scratch of the block's size. */
+static void block_bicgstab(const wco_ctx *c, const blockmap *B, int iters, cplx *r, cplx *z, cplx *q,
+                           cplx *t1, cplx *t2)
+{
+    const long N = B->Ne * 12;
+    cplx *rh = calloc(N, sizeof(cplx)), *p = calloc(N, sizeof(cplx)), *v = calloc(N, sizeof(cplx));
+    cplx *s = calloc(N, sizeof(cplx));
+    memcpy(rh, r, sizeof(cplx) * N);
+    cplx rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    for (int k = 0; k < iters; k++) {
+        const cplx rho = vdot(N, rh, r);
+        if (rho == 0.0) break;
+        const cplx beta = (rho / rho_old) * (alpha / omega);
+        for (long i = 0; i < N; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        block_schur(c, B, p, v, t1, t2);
+        const cplx rv = vdot(N, rh, v);
+        if (rv == 0.0) break;
+        alpha = rho / rv;
+        for (long i = 0; i < N; i++) s[i] = r[i] - alpha * v[i];
+        block_schur(c, B, s, q, t1, t2);   /* q = t = Dhat_B s */
+        const double tt = creal(vdot(N, q, q));
+        omega = tt == 0.0 ? 0.0 : vdot(N, q, s) / tt;
+        for (long i = 0; i < N; i++) {
+            z[i] += alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * q[i];
+        }
+        rho_old = rho;
+        if (tt == 0.0) break;
+    }
+    free(rh); free(p); free(v); free(s);
+}
+
 /* The restricted block solves of one Schwarz application on the blocks of
  * one colour (colour < 0: every block).  Colour of a block = the parities of
  * its block coordinates, bit mu for direction mu (16 colours).  The restricted
@@ -797,17 +833,21 @@ static int ras_blocks(const wco_ctx *c, const int block[4], int overlap, int ite
         for (long l = 0; l < B.Ne; l++)
             for (int i = 0; i < 12; i++) r[l * 12 + i] = vin[B.g[l] * 12 + i];
         block_mask(c, &B, r, 0);
-        /* from z = 0, r = r_B: minimal residual (alpha = <q, r> / <q, q>) or
-         * block Jacobi (alpha = 1), with q = Dhat_B r */
-        for (int k = 0; k < iters; k++) {
-            block_schur(c, &B, r, q, t1, t2);
-            cplx alpha = 1.0;
-            if (solver == 0) {
-                const double qq = creal(vdot(N, q, q));
-                if (qq == 0.0) break;
-                alpha = vdot(N, q, r) / qq;
+        if (solver == 2) {
+            block_bicgstab(c, &B, iters, r, z, q, t1, t2);
+        } else {
+            /* from z = 0, r = r_B: minimal residual (alpha = <q, r> / <q, q>)
+             * or block Jacobi (alpha = 1), with q = Dhat_B r */
+            for (int k = 0; k < iters; k++) {
+                block_schur(c, &B, r, q, t1, t2);
+                cplx alpha = 1.0;
+                if (solver == 0) {
+                    const double qq = creal(vdot(N, q, q));
+                    if (qq == 0.0) break;
+                    alpha = vdot(N, q, r) / qq;
+                }
+                for (long i = 0; i < N; i++) { z[i] += alpha * r[i]; r[i] -= alpha * q[i]; }
             }
-            for (long i = 0; i < N; i++) { z[i] += alpha * r[i]; r[i] -= alpha * q[i]; }
         }
         /* restriction: keep the even core sites (cores never overlap) */
         for (long l = 0; l < B.Ne; l++) {
@@ -826,7 +866,7 @@ static int ras_blocks(const wco_ctx *c, const int block[4], int overlap, int ite
 
 static int ras_args_ok(const wco_ctx *c, const int block[4], int overlap, int solver)
 {
-    if (solver != 0 && solver != 1) return 0;
+    if (solver < 0 || solver > 2) return 0;
     for (int mu = 0; mu < 4; mu++) {
         if (block[mu] < 2 || (block[mu] & 1) || c->L[mu] % block[mu]) return 0;
         if (c->L[mu] < block[mu] + 2 * overlap || overlap < 0) return 0;

@@ -60,7 +60,8 @@ void wco_reconstruct(const wco_ctx *c, const double *b, const double *xe, double
 
 /* Overlapped restricted additive Schwarz (one application) on even vectors.
  * solver 0: minimal residual steps from z = 0; solver 1: the linear block
- * Jacobi (Richardson) steps z <- z + (r_B - Dhat_B z) from z = 0. */
+ * Jacobi (Richardson) steps z <- z + (r_B - Dhat_B z) from z = 0; solver 2:
+ * `iters` BiCGStab iterations (two block applications each) from z = 0. */
 int wco_ras(const wco_ctx *c, const int block[4], int overlap, int iters, int solver,
             const double *in, double *out);
 /* Multiplicative Schwarz on even vectors: the 16 block colours (parities of

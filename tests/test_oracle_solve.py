@@ -109,12 +109,44 @@ def test_neumann_series_small_kappa():
     assert rel(o.clover(b), b - csw * kappa * o.clover_C(b)) < 1e-15
 
 
+def _bicgstab_steps(A, b, iters):
+    """`iters` BiCGStab iterations on A x = b from x = 0, shadow residual b
+    (van der Vorst 1992); stops when rho or <rh, v> is exactly zero."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rh = b.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho_old = alpha = omega = 1.0
+    for _ in range(iters):
+        rho = np.vdot(rh, r)
+        if rho == 0:
+            break
+        p = r + (rho / rho_old) * (alpha / omega) * (p - omega * v)
+        v = A(p)
+        rv = np.vdot(rh, v)
+        if rv == 0:
+            break
+        alpha = rho / rv
+        s_ = r - alpha * v
+        t = A(s_)
+        tt = np.vdot(t, t).real
+        omega = np.vdot(t, s_) / tt if tt != 0 else 0.0
+        x = x + alpha * p + omega * s_
+        r = s_ - omega * t
+        rho_old = rho
+        if tt == 0:
+            break
+    return x
+
+
 def _ras_bruteforce(o, dims, U, v, block, overlap, iters, solver=0, colour=None):
     """RAS from the pinned global operator: per block, a copy of the oracle on a
     gauge field that keeps only the links between locally adjacent sites of the
     extended block (all other links zero), so its hop is the Dirichlet block
-    hop; minimal residual (solver 0) or block Jacobi steps with alpha = 1
-    (solver 1) in numpy; keep the even core sites."""
+    hop; minimal residual (solver 0), block Jacobi steps with alpha = 1
+    (solver 1) or BiCGStab iterations (solver 2) in numpy; keep the even core
+    sites."""
     V = len(v)
     X = coords(dims)
     even = parity(dims) == 0
@@ -154,7 +186,9 @@ def _ras_bruteforce(o, dims, U, v, block, overlap, iters, solver=0, colour=None)
 
         r = v * mask_e
         z = np.zeros_like(v)
-        for _ in range(iters):
+        if solver == 2:
+            z = _bicgstab_steps(dhat, r, iters)
+        for _ in range(iters if solver != 2 else 0):
             q = dhat(r)
             alpha = np.vdot(q, r) / np.vdot(q, q).real if solver == 0 else 1.0
             z = z + alpha * r
@@ -166,7 +200,7 @@ def _ras_bruteforce(o, dims, U, v, block, overlap, iters, solver=0, colour=None)
     return out
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 @pytest.mark.parametrize("dims,block,overlap", [((4, 4, 4, 4), (2, 2, 2, 2), 1),
                                                 ((8, 4, 4, 4), (4, 2, 2, 2), 1),
                                                 ((4, 4, 4, 8), (2, 2, 2, 4), 0)])
@@ -245,7 +279,7 @@ def test_ras_rejects_unknown_block_solver():
     o = oracle.Oracle(dims, -1, 0.125, 1.0, synth.su3_field(dims, 3))
     v = synth.gaussian_spinor(dims, 4)
     with pytest.raises(ValueError):
-        o.ras(v, (4, 4, 4, 4), 1, 4, 2)
+        o.ras(v, (4, 4, 4, 4), 1, 4, 3)
 
 
 @pytest.mark.parametrize("dims,block,overlap", [((4, 4, 4, 8), (2, 2, 2, 2), 1), ((8, 4, 4, 4), (2, 2, 2, 2), 0)])
@@ -267,3 +301,35 @@ def test_sap_bruteforce(dims, block, overlap):
     assert rel(got, z) < 1e-13
     # a better preconditioner than the additive one on the same blocks
     assert rel(o.schur(got), v) < rel(o.schur(o.ras(v, block, overlap, 4)), v)
+
+
+def test_ras_block_solvers_reach_exact_block_solve(dense4):
+    """With enough steps, the minimal-residual and BiCGStab block solvers both
+    reach the exact block solution: Schwarz with 2^4 cores and no overlap on
+    4^4, each block system solved densely from the assembled D restricted to
+    the block (its even/odd Schur complement, T_ee^-1 form)."""
+    o, D = dense4
+    X = coords(DIMS4)
+    even = parity(DIMS4) == 0
+    v = synth.gaussian_spinor(DIMS4, 87)
+    v[~even] = 0
+    exact = np.zeros_like(v)
+    k2 = o.kappa ** 2
+    for bi in range(16):
+        org = [((bi >> mu) & 1) * 2 for mu in range(4)]
+        inside = np.all((X >= org) & (X < np.array(org) + 2), axis=1)
+        ie = np.flatnonzero(inside & even)
+        io = np.flatnonzero(inside & ~even)
+        idx = lambda sites: (sites[:, None] * 12 + np.arange(12)).reshape(-1)
+        E, O = idx(ie), idx(io)
+        Dee, Deo, Doe, Doo = D[np.ix_(E, E)], D[np.ix_(E, O)], D[np.ix_(O, E)], D[np.ix_(O, O)]
+        S = Dee - Deo @ np.linalg.solve(Doo, Doe)   # = T_ee - k^2 H_eo T_oo^-1 H_oe
+        # Dhat_B z = r with Dhat = T_ee^-1 S  <=>  S z = T_ee r
+        z = np.linalg.solve(S, Dee @ v.reshape(-1)[E])
+        exact.reshape(-1)[E] = z
+    assert np.abs(exact[~even]).max() == 0
+    mr = o.ras(v, (2, 2, 2, 2), 0, 300, 0)
+    assert rel(mr, exact) < 1e-10
+    errs = [rel(o.ras(v, (2, 2, 2, 2), 0, it, 2), exact) for it in (1, 2, 4, 8, 12)]
+    print("BiCGStab block-solve errors", errs)
+    assert errs[0] > 1e-3 and errs[1] < errs[0] and min(errs) < 1e-12
