@@ -108,15 +108,29 @@ enum { WCL_OP_HOP = 0, WCL_OP_CLOVER = 1, WCL_OP_CLOVER_INV = 2, WCL_OP_SCHUR = 
 int wcl_apply_op(wcl_ctx *ctx, int op, const double *in_dev, double *out_dev, int nrhs, int prec);
 /* Schwarz settings of WCL_OP_RAS (a solve sets them from its options):
  * overlap (extension of the cores on every side), iters (block steps), the
- * block solver -- WCL_RAS_MR, minimal residual from zero (the default), or
- * WCL_RAS_JACOBI, the linear alternative z <- z + (r_B - Dhat_B z) -- and the
- * scheme: multiplicative = 0 is the additive (restricted) Schwarz of the
- * paper; 1 runs the 16 block colours (parities of the block coordinates) in
- * turn, each on the residual in - Dhat z left by the colours before it (the
- * paper leaves the Schwarz variant open, Sec. 2).  WCL_EINVAL when the
- * extended block does not fit the lattice or one workgroup. */
-enum { WCL_RAS_MR = 0, WCL_RAS_JACOBI = 1 };
+ * block solver -- WCL_RAS_MR, minimal residual from zero (the default),
+ * WCL_RAS_JACOBI, the linear alternative z <- z + (r_B - Dhat_B z), or
+ * WCL_RAS_BICGSTAB, `iters` BiCGStab iterations (two block applications
+ * each) from zero -- and the scheme: multiplicative = 0 is the additive
+ * (restricted) Schwarz of the paper; 1 runs the 16 block colours (parities
+ * of the block coordinates) in turn, each on the residual in - Dhat z left by
+ * the colours before it (the paper leaves the Schwarz variant open, Sec. 2).
+ * The cores are the layout's tiles unless wcl_set_ras_cores set others.
+ * Tile cores with MR or Jacobi and an extended block of at most 648 sites
+ * per parity run as one fused kernel (block vectors in LDS); every other
+ * setting runs the block solves with the block vectors in device memory
+ * (the context allocates them here: 8 or 4 FP32 fields of the extended
+ * blocks' size, with BiCGStab or not).  WCL_EINVAL when the extended block
+ * does not fit the lattice, for an unknown solver, and for multiplicative
+ * Schwarz outside the fused kernel's settings; the settings then stay. */
+enum { WCL_RAS_MR = 0, WCL_RAS_JACOBI = 1, WCL_RAS_BICGSTAB = 2 };
 int wcl_set_ras(wcl_ctx *ctx, int overlap, int iters, int solver, int multiplicative);
+/* Schwarz cores (paper Sec. 2 leaves their size open): cores[mu] even,
+ * dividing L[mu], with L[mu] >= cores[mu] + 2 overlap; cores = NULL or all
+ * zero restores the tiles.  Explicit cores, even equal to the tiles, select
+ * the device-memory block path (additive Schwarz only).  WCL_EINVAL
+ * otherwise, leaving the cores as they were. */
+int wcl_set_ras_cores(wcl_ctx *ctx, const int cores[4]);
 
 /* Solver options. */
 /* FBICGSTAB: FP64 flexible BiCGStab on the even/odd system, preconditioned
@@ -137,7 +151,7 @@ typedef struct {
     int use_graph;       /* replay the inner iteration as a captured hipGraph        */
     int check_every;     /* inner iterations between host convergence checks         */
     int adjoint;         /* 1: solve D^dag x = b instead, as x = g5 D^-1 (g5 b)      */
-    int ras_solver;      /* WCL_RAS_MR or WCL_RAS_JACOBI (block solver of the RAS)   */
+    int ras_solver;      /* WCL_RAS_MR, WCL_RAS_JACOBI or WCL_RAS_BICGSTAB (RAS block solver) */
     int inner_vec_prec;  /* 32, or 16: the inner solver's vectors stored in FP16 (FP32
                           * arithmetic; needs inner_prec 16)                        */
     int ras_mult;        /* 1: multiplicative Schwarz (colour sweeps), see wcl_set_ras */

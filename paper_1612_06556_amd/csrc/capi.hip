@@ -64,6 +64,9 @@ struct wcl_ctx {
     bool have_gauge = false, have_params = false;
     int ras_overlap = 1, ras_iters = 4, ras_solver = WCL_RAS_MR;
     int ras_mult = 0;   // 1: multiplicative Schwarz (colour sweeps) instead of additive
+    int ras_cores[4] = {0, 0, 0, 0};   // explicit Schwarz cores (0: the tiles, fused kernel)
+    GrasPlan gras{};                   // block fields of the global-memory Schwarz path
+    bool gras_ready = false;
     std::vector<Buf> ws;        // workspace, indexed by slot
     double *partials = nullptr; // [cap][6][RED_BLOCKS]
     Scalars *sc = nullptr;      // [3][cap]: outer, inner, final/scratch scalars per right-hand side
@@ -204,9 +207,27 @@ int run_hop(wcl_ctx *c, const HopLaunch &L)
     return profiled(c, WCL_K_HOP, b, f, [&] { return launch_hop(L, c->st); });
 }
 
+// The Schwarz settings need the global-memory block path: explicit cores,
+// the BiCGStab block solver, or an extended block beyond the fused kernel's
+// LDS (or wider than the neighbouring tile).
+bool ras_generic(const wcl_ctx *c)
+{
+    if (c->ras_cores[0] || c->ras_solver == WCL_RAS_BICGSTAB || !gras_fits_fused(c->g, c->ras_overlap)) return true;
+    for (int mu = 0; mu < 4; mu++)
+        if (c->ras_overlap > c->g.B[mu]) return true;
+    return false;
+}
+
+int ensure_gras(wcl_ctx *c);
+
 int run_ras(wcl_ctx *c, const RasLaunch &R)
 {
     double b = 0, f = 0;
+    if (ras_generic(c)) {
+        CHK(ensure_gras(c));
+        if (c->prof) gras_work(c->gras, R, c->ras_solver, &b, &f);
+        return profiled(c, WCL_K_RAS, b, f, [&] { return launch_gras(c->gras, R, c->ras_solver, c->st); });
+    }
     if (c->prof) ras_work(R, &b, &f);
     return profiled(c, WCL_K_RAS, b, f, [&] { return launch_ras(R, c->st); });
 }
@@ -420,9 +441,40 @@ enum Slot {
     S_SU3,
     // multiplicative Schwarz: residual, Dhat z, Schur odd temporary
     S_SAPR, S_SAPT, S_SAPO,
+    // global-memory Schwarz path: tables, block fields, per-block state
+    S_GRAS_T, S_GRAS_V, S_GRAS_S,
     // bench copies start here
     S_BENCH = 64,
 };
+
+// Tables and block fields of the global-memory Schwarz path for the current
+// settings (rebuilt when the cores, overlap or the solver's field count change).
+int ensure_gras(wcl_ctx *c)
+{
+    if (!ras_generic(c)) return WCL_OK;
+    const int *cores = c->ras_cores[0] ? c->ras_cores : c->g.B;
+    const int need = gras_fields(c->ras_solver);
+    GrasPlan &P = c->gras;
+    bool same = c->gras_ready && P.overlap == c->ras_overlap && P.nvec >= need;
+    for (int mu = 0; mu < 4; mu++) same = same && P.cores[mu] == cores[mu];
+    if (same) return WCL_OK;
+    c->gras_ready = false;
+    GrasPlan Q{};
+    std::vector<uint32_t> host;
+    if (gras_tables(c->g, cores, c->ras_overlap, &Q, host) != hipSuccess)
+        return fail(WCL_EINVAL, "Schwarz cores must be even, divide the lattice and fit with the overlap");
+    Q.nvec = need;
+    void *t, *v, *st;
+    CHK(wsget(c, S_GRAS_T, host.size() * sizeof(uint32_t), &t));
+    CHK(wsget(c, S_GRAS_V, gras_vector_bytes(Q), &v));
+    CHK(wsget(c, S_GRAS_S, gras_state_bytes(Q), &st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(t, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    gras_bind(&Q, t, v, st);
+    P = Q;
+    c->gras_ready = true;
+    return WCL_OK;
+}
 
 // Largest SU(3) defect accepted for two-row link storage (the FP32 tier's
 // own rounding is 6e-8).
@@ -611,16 +663,40 @@ int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver, int multiplicati
     if (c && multiplicative != 0 && multiplicative != 1) return fail(WCL_EINVAL, "multiplicative must be 0 or 1");
     if (!c) return fail(WCL_EINVAL, "null context");
     if (overlap < 0 || iters < 1) return fail(WCL_EINVAL, "overlap >= 0 and iters >= 1 required");
-    if (solver != WCL_RAS_MR && solver != WCL_RAS_JACOBI) return fail(WCL_EINVAL, "unknown RAS block solver");
+    if (solver != WCL_RAS_MR && solver != WCL_RAS_JACOBI && solver != WCL_RAS_BICGSTAB)
+        return fail(WCL_EINVAL, "unknown RAS block solver");
+    const int *cores = c->ras_cores[0] ? c->ras_cores : c->g.B;
     for (int mu = 0; mu < 4; mu++)
-        if (overlap > c->g.B[mu] || c->g.L[mu] < c->g.B[mu] + 2 * overlap)
-            return fail(WCL_EINVAL, "RAS extended block does not fit the lattice");
-    if (ras_threads(c->g, overlap) > 1024) return fail(WCL_EINVAL, "RAS extended block too large for one workgroup");
+        if (c->g.L[mu] < cores[mu] + 2 * overlap) return fail(WCL_EINVAL, "RAS extended block does not fit the lattice");
+    const int o0 = c->ras_overlap, i0 = c->ras_iters, s0 = c->ras_solver, m0 = c->ras_mult;
     c->ras_overlap = overlap;
     c->ras_iters = iters;
     c->ras_solver = solver;
+    c->ras_mult = 0;
+    if (multiplicative && ras_generic(c)) {
+        c->ras_overlap = o0; c->ras_iters = i0; c->ras_solver = s0; c->ras_mult = m0;
+        return fail(WCL_EINVAL, "multiplicative Schwarz needs tile cores, a minimal-residual or Jacobi block "
+                                "solver and an extended block of at most 648 sites per parity");
+    }
     c->ras_mult = multiplicative;
-    return WCL_OK;
+    return ensure_gras(c);
+}
+
+int wcl_set_ras_cores(wcl_ctx *c, const int cores[4])
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    int nc[4] = {0, 0, 0, 0};
+    if (cores && (cores[0] || cores[1] || cores[2] || cores[3])) {
+        for (int mu = 0; mu < 4; mu++) {
+            if (cores[mu] < 2 || (cores[mu] & 1) || c->g.L[mu] % cores[mu] ||
+                c->g.L[mu] < cores[mu] + 2 * c->ras_overlap)
+                return fail(WCL_EINVAL, "Schwarz cores must be even, divide the lattice and fit with the overlap");
+            nc[mu] = cores[mu];
+        }
+        if (c->ras_mult) return fail(WCL_EINVAL, "explicit cores run the additive Schwarz only");
+    }
+    for (int mu = 0; mu < 4; mu++) c->ras_cores[mu] = nc[mu];
+    return ensure_gras(c);
 }
 
 int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, int prec)

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "wcl_common.h"
 
 namespace wcl {
@@ -165,6 +167,34 @@ struct RasLaunch {
     bool accumulate;     // add the restricted block results to out (else write them)
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
+
+// Schwarz block solves with the block vectors in global memory (any core
+// size and overlap that fit the lattice; block solver 0 minimal residual,
+// 1 Jacobi, 2 BiCGStab).  A plan holds the geometry tables and the block
+// fields; the caller owns the device buffers (tables, vectors, state).
+struct GrasPlan {
+    int cores[4], overlap;
+    int nblk, ne, nep;          // blocks; sites per parity of an extended block; ne padded to 64
+    int nvec;                   // block fields held (4 for minimal residual / Jacobi, 8 for BiCGStab)
+    const uint32_t *gm;         // [2][nblk][nep] global half index | t-boundary bits
+    const uint32_t *nb;         // [2][nep][4] local neighbour indices (0xffff: outside)
+    const uint8_t *core;        // [nep] even local site in the core
+    float2 *vec[8];             // block fields [nblk][12][nep] FP32
+    void *state;                // per-block solver state
+};
+int gras_fields(int solver);
+// Whether the fused LDS kernel can hold the extended block of tile cores.
+bool gras_fits_fused(const Geom &g, int overlap);
+// Geometry of a plan (validates the cores) and the host image of its tables.
+hipError_t gras_tables(const Geom &g, const int cores[4], int overlap, GrasPlan *P, std::vector<uint32_t> &host);
+// Point the plan at its device buffers (tables as uploaded from the host image).
+void gras_bind(GrasPlan *P, void *tables, void *vectors, void *state);
+size_t gras_vector_bytes(const GrasPlan &P);
+size_t gras_state_bytes(const GrasPlan &P);
+// One Schwarz application out_e = M in_e over every right-hand side of L
+// (additive only: L.colour == 0, L.accumulate false).
+hipError_t launch_gras(const GrasPlan &P, const RasLaunch &L, int solver, hipStream_t st);
+void gras_work(const GrasPlan &P, const RasLaunch &L, int solver, double *bytes, double *flops);
 
 // Gradient (FP64): K field [2][6][9][Vh] double2 scratch, G = link field.
 hipError_t launch_grad(const Geom &g, const void *u64, const void *X, const void *Y, void *K, double kappa,

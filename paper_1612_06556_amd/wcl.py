@@ -22,7 +22,7 @@ WCL_OK, WCL_EINVAL, WCL_ENOMEM, WCL_EHIP, WCL_ENOCONV, WCL_EBREAKDOWN, WCL_ENAN,
     0, -1, -2, -3, -4, -5, -6, -7)
 OP_HOP, OP_CLOVER, OP_CLOVER_INV, OP_SCHUR, OP_SCHUR_RHS, OP_RAS, OP_D, OP_DDAG = range(8)
 OUTER_FBICGSTAB, OUTER_DC, OUTER_PLAIN64, OUTER_PLAIN64_EO = 0, 1, 2, 3
-RAS_MR, RAS_JACOBI = 0, 1
+RAS_MR, RAS_JACOBI, RAS_BICGSTAB = 0, 1, 2
 
 
 class WclError(RuntimeError):
@@ -74,6 +74,7 @@ def load():
     lib.wcl_set_gauge.argtypes = [_vp, _vp]
     lib.wcl_set_params.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
     lib.wcl_set_ras.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.wcl_set_ras_cores.argtypes = [_vp, _ip]
     lib.wcl_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply_op.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int]
     lib.wcl_default_opts.argtypes = [ctypes.POINTER(wcl_solve_opts)]
@@ -134,6 +135,11 @@ def wcl_set_params(h, kappa, csw):
 
 def wcl_set_ras(h, overlap, iters, solver=0, multiplicative=0):
     _check(load().wcl_set_ras(h, int(overlap), int(iters), int(solver), int(multiplicative)))
+
+
+def wcl_set_ras_cores(h, cores):
+    arr = None if cores is None else (ctypes.c_int * 4)(*[int(c) for c in cores])
+    _check(load().wcl_set_ras_cores(h, arr))
 
 
 def wcl_apply(h, in_ptr, out_ptr, nrhs, dagger, prec):
@@ -280,9 +286,13 @@ class Lattice:
         return out
 
     def set_ras(self, overlap=1, iters=4, solver=0, multiplicative=0):
-        """Schwarz overlap, block steps, block solver (RAS_MR or RAS_JACOBI) and
-        scheme (0 additive, 1 multiplicative colour sweeps)."""
+        """Schwarz overlap, block steps, block solver (RAS_MR, RAS_JACOBI or
+        RAS_BICGSTAB) and scheme (0 additive, 1 multiplicative colour sweeps)."""
         wcl_set_ras(self.h, overlap, iters, solver, multiplicative)
+
+    def set_ras_cores(self, cores=None):
+        """Schwarz cores (4 even extents dividing the lattice); None: the tiles."""
+        wcl_set_ras_cores(self.h, cores)
 
     def solve(self, b, raise_on_error=True, **kw):
         b, nrhs = self._spinors(b)
