@@ -336,6 +336,17 @@ def sweep(opts, torch, synth, wcl):
                      ("multiplicative_mr_overlap0_iters4", dict(ras_mult=1, ras_overlap=0)),
                      ("no_ras", dict(use_ras=0))):
         schwarz[name] = _timed_solve(lat, b, torch, **dict(opts, **kw))
+    # the block solves with block vectors in device memory: BiCGStab block
+    # solver, overlap 2, 8^4 cores, and the fused kernel's own setting
+    for name, cores, kw in (("bicgstab_overlap1_iters2", None, dict(ras_solver=wcl.RAS_BICGSTAB, ras_iters=2)),
+                            ("bicgstab_overlap1_iters1", None, dict(ras_solver=wcl.RAS_BICGSTAB, ras_iters=1)),
+                            ("mr_overlap2_iters4", None, dict(ras_overlap=2)),
+                            ("mr_cores8_overlap1_iters4", (8, 8, 8, 8), {}),
+                            ("mr_cores8_overlap2_iters4", (8, 8, 8, 8), dict(ras_overlap=2)),
+                            ("mr_overlap1_iters4_device_memory_path", (4, 4, 4, 4), {})):
+        lat.set_ras_cores(cores)
+        schwarz[name] = _timed_solve(lat, b, torch, **dict(opts, **kw))
+    lat.set_ras_cores(None)
     out["schwarz_24x24x24x32"] = schwarz
     print("sweep: Schwarz variants done", file=sys.stderr, flush=True)
     stol = {}
