@@ -200,7 +200,9 @@ int wcl_bench_clover(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_pe
 int wcl_bench_stream(wcl_ctx *ctx, double mib, int reps, double *read_gbs, double *copy_gbs);
 
 /* Kernel-class profiling on the context's stream: with profiling enabled,
- * every launch of the classes below is bracketed by HIP events and its
+ * every launch of the classes below is timed by HIP events (carried in the
+ * kernel's dispatch packet for the single-kernel hop, RAS and clover
+ * launches; recorded around multi-kernel launches) and its
  * algorithmic HBM bytes and flops are recorded (1320 flop per hop site,
  * 504 per clover site; bytes = each link, clover site and vector once).
  * wcl_profile(ctx, 1) clears and starts, (ctx, 0) stops; wcl_profile_read
@@ -216,6 +218,11 @@ typedef struct {
 } wcl_kstat;
 int wcl_profile(wcl_ctx *ctx, int enable);
 int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
+/* Classes whose launches carry timing events while profiling (bit k = class
+ * WCL_K_k; default all).  Every profiled launch costs a few microseconds of
+ * queue time for its events; launches of the other classes are still counted
+ * (launches, bytes, flops) with ms = 0.  WCL_EINVAL for other bits. */
+int wcl_profile_mask(wcl_ctx *ctx, int mask);
 
 /* Launch configuration of the hopping kernel: threads per workgroup (64, 128,
  * 256), pipeline depth (2, 3: hops of a site whose neighbour spinor and

@@ -82,6 +82,7 @@ struct wcl_ctx {
         double bytes, flops;
     };
     bool prof = false;
+    int prof_mask = (1 << WCL_K_COUNT) - 1;   // classes whose launches carry timing events
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     wcl_kstat stats[WCL_K_COUNT];
@@ -186,17 +187,31 @@ template <typename F>
 int profiled(wcl_ctx *c, int kclass, double bytes, double flops, F &&launch)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->prof) {
+    const bool timed = c->prof && ((c->prof_mask >> kclass) & 1);
+    if (timed) {
         e0 = take_event(c);
         e1 = take_event(c);
         if (!e0 || !e1) return fail(WCL_EHIP, "hipEventCreate failed");
         HIPCHK(hipEventRecord(e0, c->st));
     }
     HIPCHK(launch());
-    if (c->prof) {
-        HIPCHK(hipEventRecord(e1, c->st));
-        c->recs.push_back({kclass, e0, e1, bytes, flops});
+    if (timed) HIPCHK(hipEventRecord(e1, c->st));
+    if (c->prof) c->recs.push_back({kclass, e0, e1, bytes, flops});
+    return WCL_OK;
+}
+
+// A single-kernel launch timed by events in its own dispatch packet.
+template <typename F>
+int profiled_ev(wcl_ctx *c, int kclass, double bytes, double flops, F &&launch)
+{
+    LaunchEvents ev{nullptr, nullptr};
+    if (c->prof && ((c->prof_mask >> kclass) & 1)) {
+        ev.start = take_event(c);
+        ev.stop = take_event(c);
+        if (!ev.start || !ev.stop) return fail(WCL_EHIP, "hipEventCreate failed");
     }
+    HIPCHK(launch(ev));
+    if (c->prof) c->recs.push_back({kclass, ev.start, ev.stop, bytes, flops});
     return WCL_OK;
 }
 
@@ -204,7 +219,11 @@ int run_hop(wcl_ctx *c, const HopLaunch &L)
 {
     double b = 0, f = 0;
     if (c->prof) hop_work(L, &b, &f);
-    return profiled(c, WCL_K_HOP, b, f, [&] { return launch_hop(L, c->st); });
+    return profiled_ev(c, WCL_K_HOP, b, f, [&](const LaunchEvents &ev) {
+        HopLaunch T = L;
+        T.ev = ev;
+        return launch_hop(T, c->st);
+    });
 }
 
 // The Schwarz settings need the global-memory block path: explicit cores,
@@ -229,7 +248,11 @@ int run_ras(wcl_ctx *c, const RasLaunch &R)
         return profiled(c, WCL_K_RAS, b, f, [&] { return launch_gras(c->gras, R, c->ras_solver, c->st); });
     }
     if (c->prof) ras_work(R, &b, &f);
-    return profiled(c, WCL_K_RAS, b, f, [&] { return launch_ras(R, c->st); });
+    return profiled_ev(c, WCL_K_RAS, b, f, [&](const LaunchEvents &ev) {
+        RasLaunch T = R;
+        T.ev = ev;
+        return launch_ras(T, c->st);
+    });
 }
 
 int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc,
@@ -265,8 +288,8 @@ int run_clover(wcl_ctx *c, int lp, int sp, int p, const void *clov, const void *
 {
     const double sb = sp == P64 ? 192.0 : sp == P32 ? 96.0 : 48.0;
     const double cb = lp == P64 ? 576.0 : lp == P32 ? 288.0 : 144.0;
-    return profiled(c, WCL_K_CLOVER, (2 * sb * nrhs + cb) * c->Vh, 504.0 * c->Vh * nrhs, [&] {
-        return launch_clover(c->g, lp, sp, p, clov, in, out, c->st, nrhs, in_stride, out_stride);
+    return profiled_ev(c, WCL_K_CLOVER, (2 * sb * nrhs + cb) * c->Vh, 504.0 * c->Vh * nrhs, [&](const LaunchEvents &ev) {
+        return launch_clover(c->g, lp, sp, p, clov, in, out, c->st, nrhs, in_stride, out_stride, ev);
     });
 }
 
@@ -1521,12 +1544,20 @@ extern "C" int wcl_profile(wcl_ctx *c, int enable)
     if (!c) return fail(WCL_EINVAL, "null context");
     HIPCHK(hipStreamSynchronize(c->st));
     for (auto &r : c->recs) {
-        c->pool.push_back(r.e0);
-        c->pool.push_back(r.e1);
+        if (r.e0) c->pool.push_back(r.e0);
+        if (r.e1) c->pool.push_back(r.e1);
     }
     c->recs.clear();
     memset(c->stats, 0, sizeof(c->stats));
     c->prof = enable != 0;
+    return WCL_OK;
+}
+
+extern "C" int wcl_profile_mask(wcl_ctx *c, int mask)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    if (mask < 0 || mask >= (1 << WCL_K_COUNT)) return fail(WCL_EINVAL, "mask holds bits of WCL_K_* classes only");
+    c->prof_mask = mask;
     return WCL_OK;
 }
 
@@ -1536,7 +1567,7 @@ extern "C" int wcl_profile_read(wcl_ctx *c, int kclass, wcl_kstat *out)
     HIPCHK(hipStreamSynchronize(c->st));
     for (auto &r : c->recs) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+        if (r.e0) HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
         wcl_kstat &k = c->stats[r.kclass];
         if (r.flops > 0.0) {  // launches that did work (not no-ops queued past convergence)
             k.launches += 1;
@@ -1547,8 +1578,8 @@ extern "C" int wcl_profile_read(wcl_ctx *c, int kclass, wcl_kstat *out)
             k.idle_launches += 1;
             k.idle_ms += ms;
         }
-        c->pool.push_back(r.e0);
-        c->pool.push_back(r.e1);
+        if (r.e0) c->pool.push_back(r.e0);
+        if (r.e1) c->pool.push_back(r.e1);
     }
     c->recs.clear();
     *out = c->stats[kclass];

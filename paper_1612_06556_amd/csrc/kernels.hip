@@ -754,9 +754,9 @@ static hipError_t hop_mr_dispatch(const HopLaunch &L, const HopArgs &a, dim3 blo
     const int ngr = (a.nrhs + NR - 1) / NR;
     dim3 grid(((a.g.Vh + block.x - 1) / block.x) * ngr);
     switch (L.mode) {
-    case HOP: k_hop_mr<SL, HOP, NR><<<grid, block, 0, st>>>(a); break;
-    case CLOV_H: k_hop_mr<SL, CLOV_H, NR><<<grid, block, 0, st>>>(a); break;
-    case XPAY: k_hop_mr<SL, XPAY, NR><<<grid, block, 0, st>>>(a); break;
+    case HOP: ext_launch(k_hop_mr<SL, HOP, NR>, grid, block, 0, st, L.ev, a); break;
+    case CLOV_H: ext_launch(k_hop_mr<SL, CLOV_H, NR>, grid, block, 0, st, L.ev, a); break;
+    case XPAY: ext_launch(k_hop_mr<SL, XPAY, NR>, grid, block, 0, st, L.ev, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -777,14 +777,14 @@ static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, di
     const bool nt = L.nontemporal && a.nrhs == 1;
     // staged input spinors (depth 2, non-dagger): one LDS slot per thread
     const bool staged = L.lds_stage && !L.dagger && !nt && L.depth == 2;
-    if (staged && block.x == 64) k_hop<SL, SS, MODE, false, 2, false, 64><<<grid, block, 0, st>>>(a);
-    else if (staged && block.x == 128) k_hop<SL, SS, MODE, false, 2, false, 128><<<grid, block, 0, st>>>(a);
-    else if (staged && block.x == 256) k_hop<SL, SS, MODE, false, 2, false, 256><<<grid, block, 0, st>>>(a);
-    else if (L.dagger) k_hop<SL, SS, MODE, true, 2, false, 0><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 3 && nt) k_hop<SL, SS, MODE, false, 3, true, 0><<<grid, block, 0, st>>>(a);
-    else if (L.depth == 3) k_hop<SL, SS, MODE, false, 3, false, 0><<<grid, block, 0, st>>>(a);
-    else if (nt) k_hop<SL, SS, MODE, false, 2, true, 0><<<grid, block, 0, st>>>(a);
-    else k_hop<SL, SS, MODE, false, 2, false, 0><<<grid, block, 0, st>>>(a);
+    if (staged && block.x == 64) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 64>, grid, block, 0, st, L.ev, a);
+    else if (staged && block.x == 128) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 128>, grid, block, 0, st, L.ev, a);
+    else if (staged && block.x == 256) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 256>, grid, block, 0, st, L.ev, a);
+    else if (L.dagger) ext_launch(k_hop<SL, SS, MODE, true, 2, false, 0>, grid, block, 0, st, L.ev, a);
+    else if (L.depth == 3 && nt) ext_launch(k_hop<SL, SS, MODE, false, 3, true, 0>, grid, block, 0, st, L.ev, a);
+    else if (L.depth == 3) ext_launch(k_hop<SL, SS, MODE, false, 3, false, 0>, grid, block, 0, st, L.ev, a);
+    else if (nt) ext_launch(k_hop<SL, SS, MODE, false, 2, true, 0>, grid, block, 0, st, L.ev, a);
+    else ext_launch(k_hop<SL, SS, MODE, false, 2, false, 0>, grid, block, 0, st, L.ev, a);
 }
 
 template <typename SL, typename SS>
@@ -865,17 +865,17 @@ __global__ void __launch_bounds__(256) k_clover(Geom g, int p, const void *clov,
 }
 
 hipError_t launch_clover(const Geom &g, int lp, int sp, int p, const void *clov, const void *in, void *out,
-                         hipStream_t st, int nrhs, size_t in_stride, size_t out_stride)
+                         hipStream_t st, int nrhs, size_t in_stride, size_t out_stride, LaunchEvents ev)
 {
     dim3 grid((g.Vh + 255) / 256, nrhs), block(256);
     const char *i = (const char *)in;
     char *o = (char *)out;
     if (lp == P32C) lp = P32;
     if (lp == P16C) lp = P16;
-    if (lp == P64 && sp == P64) k_clover<double, double><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
-    else if (lp == P32 && sp == P32) k_clover<float, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
-    else if (lp == P16 && sp == P32) k_clover<__half, float><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
-    else if (lp == P16 && sp == P16) k_clover<__half, __half><<<grid, block, 0, st>>>(g, p, clov, i, o, in_stride, out_stride);
+    if (lp == P64 && sp == P64) ext_launch(k_clover<double, double>, grid, block, 0, st, ev, g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P32 && sp == P32) ext_launch(k_clover<float, float>, grid, block, 0, st, ev, g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P16 && sp == P32) ext_launch(k_clover<__half, float>, grid, block, 0, st, ev, g, p, clov, i, o, in_stride, out_stride);
+    else if (lp == P16 && sp == P16) ext_launch(k_clover<__half, __half>, grid, block, 0, st, ev, g, p, clov, i, o, in_stride, out_stride);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

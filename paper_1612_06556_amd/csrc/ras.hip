@@ -431,17 +431,17 @@ hipError_t ras_dispatch(const RasLaunch &L, const RasArgs &a, dim3 grid, dim3 bl
 {
     if (L.vec_prec == P16) {
         switch (L.link_prec) {
-            case P16: k_ras<__half, MAXNE, JAC, __half><<<grid, block, 0, st>>>(a); break;
-            case P16C: k_ras<R12h, MAXNE, JAC, __half><<<grid, block, 0, st>>>(a); break;
+            case P16: ext_launch(k_ras<__half, MAXNE, JAC, __half>, grid, block, 0, st, L.ev, a); break;
+            case P16C: ext_launch(k_ras<R12h, MAXNE, JAC, __half>, grid, block, 0, st, L.ev, a); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     switch (L.link_prec) {
-        case P32: k_ras<float, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
-        case P16: k_ras<__half, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
-        case P32C: k_ras<R12f, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
-        case P16C: k_ras<R12h, MAXNE, JAC, float><<<grid, block, 0, st>>>(a); break;
+        case P32: ext_launch(k_ras<float, MAXNE, JAC, float>, grid, block, 0, st, L.ev, a); break;
+        case P16: ext_launch(k_ras<__half, MAXNE, JAC, float>, grid, block, 0, st, L.ev, a); break;
+        case P32C: ext_launch(k_ras<R12f, MAXNE, JAC, float>, grid, block, 0, st, L.ev, a); break;
+        case P16C: ext_launch(k_ras<R12h, MAXNE, JAC, float>, grid, block, 0, st, L.ev, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,6 +1,7 @@
 // wcl_launch.h -- host-side launchers of the library's kernels (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -8,6 +9,19 @@
 #include "wcl_common.h"
 
 namespace wcl {
+
+// Start / stop events of a timed launch.  ext_launch puts them into the
+// kernel's own dispatch packet (no extra queue packets between kernels, the
+// duration is the kernel's alone); null events launch untimed.
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+template <typename... Params, typename... Args>
+inline void ext_launch(void (*k)(Params...), dim3 grid, dim3 block, uint32_t shm, hipStream_t st,
+                       const LaunchEvents &ev, Args... args)
+{
+    hipExtLaunchKernelGGL(k, grid, block, shm, st, ev.start, ev.stop, 0u, args...);
+}
 
 // Storage precision codes.  P32C / P16C: links as two rows (12 reals) in
 // FP32 / FP16, clover in FP32 / FP16; spinors never use these codes.
@@ -48,6 +62,7 @@ struct HopLaunch {
     int rhs_per_thread; // 2 or 4: batched launches keep that many right-hand sides per thread
                         // (FP32 spinors, modes HOP / CLOV_H / XPAY); else one per workgroup
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
+    LaunchEvents ev;           // timing events of the launch (null: untimed)
 };
 
 hipError_t launch_hop(const HopLaunch &a, hipStream_t st);
@@ -64,7 +79,7 @@ void ras_work(const struct RasLaunch &a, double *bytes, double *flops);
 // out = A in on parity p (A = clover field).
 hipError_t launch_clover(const Geom &g, int link_prec, int spin_prec, int p, const void *clov,
                          const void *in, void *out, hipStream_t st, int nrhs = 1, size_t in_stride = 0,
-                         size_t out_stride = 0);
+                         size_t out_stride = 0, LaunchEvents ev = {});
 
 // Canonical complex128 [V][4][3] <-> e/o FP64 field [2][12][Vh] double2.
 hipError_t launch_pack_spinor(const Geom &g, const double *canon, void *eo, hipStream_t st);
@@ -165,6 +180,7 @@ struct RasLaunch {
     int colour;          // 0: every block; k + 1: the blocks of colour k only (bit mu = parity of
                          // the block coordinate in direction mu)
     bool accumulate;     // add the restricted block results to out (else write them)
+    LaunchEvents ev;     // timing events of the launch (null: untimed)
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 

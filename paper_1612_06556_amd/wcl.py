@@ -87,6 +87,7 @@ def load():
     lib.wcl_destroy.argtypes = [_vp]
     lib.wcl_profile.argtypes = [_vp, ctypes.c_int]
     lib.wcl_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(wcl_kstat)]
+    lib.wcl_profile_mask.argtypes = [_vp, ctypes.c_int]
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     lib.wcl_set_hop_staging.argtypes = [_vp, ctypes.c_int]
@@ -194,6 +195,10 @@ def wcl_destroy(h):
 
 def wcl_profile(h, enable):
     _check(load().wcl_profile(h, int(bool(enable))))
+
+
+def wcl_profile_mask(h, mask):
+    _check(load().wcl_profile_mask(h, int(mask)))
 
 
 def wcl_profile_read(h, kclass):

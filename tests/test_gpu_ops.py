@@ -178,6 +178,30 @@ def test_ras_op_launch_accounting():
     assert st["flops"] == expect
 
 
+def test_profile_mask_times_selected_classes():
+    """With the class mask set to RAS only, RAS launches carry timing events
+    and hop launches are counted (launches, flops) with no time; the full
+    mask times both again."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, _, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = to_gpu(synth.gaussian_spinor(dims, 2001))
+    lat.set_ras(1, 4)
+    for mask, hop_timed in ((1 << wcl.K_RAS, False), (7, True)):
+        wcl.wcl_profile(lat.h, 1)
+        wcl.wcl_profile_mask(lat.h, mask)
+        lat.solve(b, tol=1e-10)
+        hop = wcl.wcl_profile_read(lat.h, wcl.K_HOP)
+        ras = wcl.wcl_profile_read(lat.h, wcl.K_RAS)
+        wcl.wcl_profile(lat.h, 0)
+        assert hop["launches"] > 0 and hop["flops"] > 0 and ras["launches"] > 0
+        assert ras["ms"] > 0
+        assert (hop["ms"] > 0) == hop_timed
+    wcl.wcl_profile_mask(lat.h, 7)
+    with pytest.raises(wcl.WclError):
+        wcl.wcl_profile_mask(lat.h, 8)
+
+
 def test_bench_entry_points():
     """wcl_bench_hop / wcl_bench_clover run on rotating copies and leave the
     context's fields intact (D still matches the oracle afterwards)."""
