@@ -130,7 +130,7 @@ def _rate(ms, Vh, flop_site, bytes_site):
 def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     """Standalone kernels (median of 5 trials of 1000 launches, cold = 4
     rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set; the
-    FP32 hop also cold with non-temporal link loads), the device's streaming
+    hops also cold with non-temporal link/clover loads), the device's streaming
     ceilings, the paper's long lattice, and time-to-solution variants against
     the plain FP64 solve."""
     out = {}
@@ -151,8 +151,11 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     tune = wcl.wcl_autotune_hop(lat.h, 32, 4)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 1)
     hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 1000, 4)), Vh, 1320, 768)
-    wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     lat.set_compression(1)
+    for prec in (32, 16):
+        ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
+        hop[f"fp{prec}_r12_cold_nontemporal"] = _rate(ms, Vh, 1320, 8 * (48 if prec == 32 else 24) + 192)
+    wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     # the same launch shape without the LDS staging of input spinors
     wcl.wcl_set_hop_staging(lat.h, 0)
     for prec in (32, 16):

@@ -466,6 +466,8 @@ enum Slot {
     S_SAPR, S_SAPT, S_SAPO,
     // global-memory Schwarz path: tables, block fields, per-block state
     S_GRAS_T, S_GRAS_V, S_GRAS_S,
+    // field strength planes of the clover setup
+    S_CLOVF,
     // bench copies start here
     S_BENCH = 64,
 };
@@ -672,8 +674,10 @@ int wcl_set_params(wcl_ctx *c, double kappa, double csw)
     c->csw = csw;
     int zero = 0, bad = 0;
     HIPCHK(hipMemcpyAsync(c->info, &zero, sizeof(int), hipMemcpyHostToDevice, c->st));
+    void *fbuf;
+    CHK(wsget(c, S_CLOVF, (size_t)6 * 9 * 2 * c->Vh * sizeof(double), &fbuf));
     HIPCHK(launch_clover_build(c->g, c->U64, csw * kappa, c->T64, c->Ti64, c->T32, c->Ti32, c->T16, c->Ti16,
-                               c->info, c->st));
+                               c->info, (double *)fbuf, c->st));
     HIPCHK(hipMemcpyAsync(&bad, c->info, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     if (bad) return fail(WCL_ENAN, std::to_string(bad) + " clover blocks are not positive definite");

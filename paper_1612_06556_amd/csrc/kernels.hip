@@ -348,24 +348,94 @@ WCL_D void pack_block(const cplx<double> A[36], double *out36)
         }
 }
 
-__global__ void __launch_bounds__(64) k_clover_build(Geom g, const void *u64, double ck, void *t64, void *ti64,
-                                                     void *t32, void *ti32, void *t16, void *ti16, int *info)
+// Clover setup in two passes.  Pass 1: one thread per (site, plane) forms the
+// traceless Hermitian F_{mu nu} and stores its upper triangle (F00, F11, F22,
+// Re/Im F01, F02, F12: 9 reals) in F[plane][9][2 Vh].  Planes: E_k = F_{k t}
+// (0..2), B_x = F_yz, -B_y = F_xz, B_z = F_xy (3..5).
+__global__ void __launch_bounds__(128) k_clover_fs(Geom g, const void *u64, double *F)
 {
+    const int n = 2 * g.Vh;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 2 * g.Vh) return;
+    if (idx >= n) return;
+    const int plane = blockIdx.y;
     const int p = idx / g.Vh;
     const int h = idx - p * g.Vh;
     const Site s = decompose(g, h, p);
-    // planes: E_k = F_{k t}, B_x = F_yz, B_y = -F_xz, B_z = F_xy
-    const M3 E0 = field_strength(g, u64, s.x, 0, 3);
-    const M3 E1 = field_strength(g, u64, s.x, 1, 3);
-    const M3 E2 = field_strength(g, u64, s.x, 2, 3);
-    const M3 Bx = field_strength(g, u64, s.x, 1, 2);
-    const M3 Bym = field_strength(g, u64, s.x, 0, 2);
-    const M3 Bz = field_strength(g, u64, s.x, 0, 1);
-    double packedT[72], packedTi[72];
-    bool ok = true;
+    // (mu, nu) of the planes: (0,3) (1,3) (2,3) (1,2) (0,2) (0,1)
+    const int mu = plane < 3 ? plane : (plane == 3 ? 1 : 0);
+    const int nu = plane < 3 ? 3 : (plane == 5 ? 1 : 2);
+    const M3 f = field_strength(g, u64, s.x, mu, nu);
+    double *o = F + (size_t)plane * 9 * n + idx;
+    o[0] = f.a[0].re;
+    o[(size_t)n] = f.a[4].re;
+    o[2 * (size_t)n] = f.a[8].re;
+    o[3 * (size_t)n] = f.a[1].re;
+    o[4 * (size_t)n] = f.a[1].im;
+    o[5 * (size_t)n] = f.a[2].re;
+    o[6 * (size_t)n] = f.a[2].im;
+    o[7 * (size_t)n] = f.a[5].re;
+    o[8 * (size_t)n] = f.a[5].im;
+}
+
+// Entry (a, b) of plane `plane` of the stored F (the lower triangle by
+// Hermiticity).
+WCL_D cplx<double> f_entry(const double *F, size_t n, int idx, int plane, int a, int b)
+{
+    const double *q = F + (size_t)plane * 9 * n + idx;
+    if (a == b) return {q[(size_t)a * n], 0.0};
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int k = lo == 0 ? (hi == 1 ? 3 : 5) : 7;
+    const double re = q[(size_t)k * n], im = q[(size_t)(k + 1) * n];
+    return a < b ? cplx<double>{re, im} : cplx<double>{re, -im};
+}
+
+// Half (chirality block chi) of a packed clover site in storage S: FP64 and
+// FP32 blocks fill whole 16-byte words; FP16 block 0 ends and block 1 starts
+// in word 4, whose other half is carried in `keep`.
+template <typename S>
+WCL_D void store_clover_block(void *base, int p, uint32_t h, uint32_t Vh, int chi, const double c[36], uint2 &keep)
+{
+    if constexpr (sizeof(S) == 8) {
 #pragma unroll
+        for (uint32_t k = 0; k < 18; k++)
+            stf(base, (((uint32_t)p * 36 + 18 * chi + k) * Vh + h) * 16u, make_double2(c[2 * k], c[2 * k + 1]));
+    } else if constexpr (sizeof(S) == 4) {
+#pragma unroll
+        for (uint32_t k = 0; k < 9; k++)
+            stf(base, (((uint32_t)p * 18 + 9 * chi + k) * Vh + h) * 16u,
+                make_float4((float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]));
+    } else {
+        uint32_t w[18];
+#pragma unroll
+        for (int k = 0; k < 18; k++) w[k] = f22h((float)c[2 * k], (float)c[2 * k + 1]);
+        if (chi == 0) {
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++)
+                stf(base, (((uint32_t)p * 9 + k) * Vh + h) * 16u, make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]));
+            keep = make_uint2(w[16], w[17]);
+        } else {
+            stf(base, (((uint32_t)p * 9 + 4) * Vh + h) * 16u, make_uint4(keep.x, keep.y, w[0], w[1]));
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++)
+                stf(base, (((uint32_t)p * 9 + 5 + k) * Vh + h) * 16u,
+                    make_uint4(w[2 + 4 * k], w[3 + 4 * k], w[4 + 4 * k], w[5 + 4 * k]));
+        }
+    }
+}
+
+// Pass 2: one thread per site builds T = 1 - c_sw kappa sigma.F one
+// chirality block at a time from the stored F, inverts it (FP64 Cholesky)
+// and writes both into every requested storage.
+__global__ void __launch_bounds__(64) k_clover_inv(Geom g, const double *F, double ck, void *t64, void *ti64,
+                                                   void *t32, void *ti32, void *t16, void *ti16, int *info)
+{
+    const size_t n = 2 * (size_t)g.Vh;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int)n) return;
+    const int p = idx / g.Vh;
+    const int h = idx - p * g.Vh;
+    bool ok = true;
+    uint2 keepT = make_uint2(0u, 0u), keepTi = make_uint2(0u, 0u);
     for (int chi = 0; chi < 2; chi++) {
         const double se = chi == 0 ? 1.0 : -1.0;
         // G_k = se * E_k - B_k
@@ -374,10 +444,9 @@ __global__ void __launch_bounds__(64) k_clover_build(Geom g, const void *u64, do
         for (int a = 0; a < 3; a++)
 #pragma unroll
             for (int b = 0; b < 3; b++) {
-                const int k = a * 3 + b;
-                const cplx<double> G1 = se * E0.a[k] - Bx.a[k];
-                const cplx<double> G2 = se * E1.a[k] + Bym.a[k];
-                const cplx<double> G3 = se * E2.a[k] - Bz.a[k];
+                const cplx<double> G1 = se * f_entry(F, n, idx, 0, a, b) - f_entry(F, n, idx, 3, a, b);
+                const cplx<double> G2 = se * f_entry(F, n, idx, 1, a, b) + f_entry(F, n, idx, 4, a, b);
+                const cplx<double> G3 = se * f_entry(F, n, idx, 2, a, b) - f_entry(F, n, idx, 5, a, b);
                 const cplx<double> iG2 = {-G2.im, G2.re};
                 const double id = (a == b) ? 1.0 : 0.0;
                 A[a * 6 + b] = cplx<double>{id, 0.0} - ck * G3;
@@ -385,25 +454,27 @@ __global__ void __launch_bounds__(64) k_clover_build(Geom g, const void *u64, do
                 A[a * 6 + 3 + b] = -ck * (G1 - iG2);
                 A[(3 + a) * 6 + b] = -ck * (G1 + iG2);
             }
+        double packed[36];
+        pack_block(A, packed);
+        if (t64) store_clover_block<double>(t64, p, h, g.Vh, chi, packed, keepT);
+        if (t32) store_clover_block<float>(t32, p, h, g.Vh, chi, packed, keepT);
+        if (t16) store_clover_block<__half>(t16, p, h, g.Vh, chi, packed, keepT);
         cplx<double> Ai[36];
         ok = hpd_inverse6(A, Ai) && ok;
-        pack_block(A, packedT + 36 * chi);
-        pack_block(Ai, packedTi + 36 * chi);
+        pack_block(Ai, packed);
+        if (ti64) store_clover_block<double>(ti64, p, h, g.Vh, chi, packed, keepTi);
+        if (ti32) store_clover_block<float>(ti32, p, h, g.Vh, chi, packed, keepTi);
+        if (ti16) store_clover_block<__half>(ti16, p, h, g.Vh, chi, packed, keepTi);
     }
     if (!ok) atomicAdd(info, 1);
-    if (t64) store_clover<double>(t64, p, h, g.Vh, packedT);
-    if (ti64) store_clover<double>(ti64, p, h, g.Vh, packedTi);
-    if (t32) store_clover<float>(t32, p, h, g.Vh, packedT);
-    if (ti32) store_clover<float>(ti32, p, h, g.Vh, packedTi);
-    if (t16) store_clover<__half>(t16, p, h, g.Vh, packedT);
-    if (ti16) store_clover<__half>(ti16, p, h, g.Vh, packedTi);
 }
 
 hipError_t launch_clover_build(const Geom &g, const void *u64, double ck, void *t64, void *ti64, void *t32,
-                               void *ti32, void *t16, void *ti16, int *info, hipStream_t st)
+                               void *ti32, void *t16, void *ti16, int *info, double *fbuf, hipStream_t st)
 {
     const int n = 2 * g.Vh;
-    k_clover_build<<<(n + 63) / 64, 64, 0, st>>>(g, u64, ck, t64, ti64, t32, ti32, t16, ti16, info);
+    k_clover_fs<<<dim3((n + 127) / 128, 6), 128, 0, st>>>(g, u64, fbuf);
+    k_clover_inv<<<(n + 63) / 64, 64, 0, st>>>(g, fbuf, ck, t64, ti64, t32, ti32, t16, ti16, info);
     return hipGetLastError();
 }
 
@@ -775,11 +846,15 @@ template <typename SL, typename SS, int MODE>
 static void hop_dispatch_dag(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st)
 {
     const bool nt = L.nontemporal && a.nrhs == 1;
-    // staged input spinors (depth 2, non-dagger): one LDS slot per thread
-    const bool staged = L.lds_stage && !L.dagger && !nt && L.depth == 2;
-    if (staged && block.x == 64) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 64>, grid, block, 0, st, L.ev, a);
-    else if (staged && block.x == 128) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 128>, grid, block, 0, st, L.ev, a);
-    else if (staged && block.x == 256) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 256>, grid, block, 0, st, L.ev, a);
+    // staged input spinors (depth 2, non-dagger): one LDS slot per thread;
+    // with non-temporal operator loads for single-use (cold) calls
+    const bool staged = L.lds_stage && !L.dagger && L.depth == 2;
+    if (staged && nt && block.x == 64) ext_launch(k_hop<SL, SS, MODE, false, 2, true, 64>, grid, block, 0, st, L.ev, a);
+    else if (staged && nt && block.x == 128) ext_launch(k_hop<SL, SS, MODE, false, 2, true, 128>, grid, block, 0, st, L.ev, a);
+    else if (staged && nt && block.x == 256) ext_launch(k_hop<SL, SS, MODE, false, 2, true, 256>, grid, block, 0, st, L.ev, a);
+    else if (staged && !nt && block.x == 64) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 64>, grid, block, 0, st, L.ev, a);
+    else if (staged && !nt && block.x == 128) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 128>, grid, block, 0, st, L.ev, a);
+    else if (staged && !nt && block.x == 256) ext_launch(k_hop<SL, SS, MODE, false, 2, false, 256>, grid, block, 0, st, L.ev, a);
     else if (L.dagger) ext_launch(k_hop<SL, SS, MODE, true, 2, false, 0>, grid, block, 0, st, L.ev, a);
     else if (L.depth == 3 && nt) ext_launch(k_hop<SL, SS, MODE, false, 3, true, 0>, grid, block, 0, st, L.ev, a);
     else if (L.depth == 3) ext_launch(k_hop<SL, SS, MODE, false, 3, false, 0>, grid, block, 0, st, L.ev, a);

@@ -98,8 +98,9 @@ hipError_t launch_stream(int copy, const void *a, void *b, size_t n16, float *ou
 // Clover T and T^-1 (FP64 arithmetic) from the FP64 links, written in all
 // three precisions.  info_dev[0] counts sites whose 6x6 block lost positive
 // definiteness during inversion (a zero or negative pivot).
+// fbuf: scratch of 6 * 9 * 2 Vh doubles (the field strength planes).
 hipError_t launch_clover_build(const Geom &g, const void *u64, double csw_kappa, void *t64, void *ti64,
-                               void *t32, void *ti32, void *t16, void *ti16, int *info_dev,
+                               void *t32, void *ti32, void *t16, void *ti16, int *info_dev, double *fbuf,
                                hipStream_t st);
 
 // Spinor precision conversion of nsites sites in sections of Vh sites (both

@@ -252,9 +252,10 @@ def test_ras_zero_blocks(prec):
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("block", [64, 128, 256])
 def test_hop_staging(case, block):
-    """Staged input spinors (LDS copy of the workgroup's own half-sites) give
-    bitwise the unstaged kernel's result for every workgroup size, on ragged
-    last workgroups and for batched right-hand sides; both match the oracle."""
+    """Staged input spinors (LDS copy of the workgroup's own half-sites), with
+    temporal or non-temporal operator loads, give bitwise the unstaged
+    kernel's result for every workgroup size, on ragged last workgroups and
+    for batched right-hand sides; all match the oracle."""
     from paper_1612_06556_amd import wcl
     dims, tbc, kappa, csw, seed, tile = case
     lat, orc, _ = setup(dims, tbc, kappa, csw, seed, tile)
@@ -265,14 +266,17 @@ def test_hop_staging(case, block):
     ge = to_gpu(pe)
     for prec in (64, 32, 16):
         res = {}
-        for stage in (1, 0):
-            wcl.wcl_set_tuning(lat.h, block, 2, 1, 0)
+        for stage, nt in ((1, 0), (0, 0), (1, 1), (0, 1)):   # staged / unstaged, temporal / non-temporal
+            wcl.wcl_set_tuning(lat.h, block, 2, 1, nt)
             wcl.wcl_set_hop_staging(lat.h, stage)
-            res[stage] = (to_host(lat.apply(g, prec=prec)), to_host(lat.apply_op(wcl.OP_HOP, g[0], prec=prec)),
-                          to_host(lat.apply_op(wcl.OP_SCHUR, ge, prec=prec)))
-        for a, b in zip(res[1], res[0]):
-            assert np.array_equal(a, b)
-        d, hop, schur = res[1]
+            res[stage, nt] = (to_host(lat.apply(g, prec=prec)), to_host(lat.apply_op(wcl.OP_HOP, g[0], prec=prec)),
+                              to_host(lat.apply_op(wcl.OP_SCHUR, ge, prec=prec)))
+        wcl.wcl_set_tuning(lat.h, 256, 2, 1, 0)
+        wcl.wcl_set_hop_staging(lat.h, 1)
+        for key in ((0, 0), (1, 1), (0, 1)):
+            for a, b in zip(res[1, 0], res[key]):
+                assert np.array_equal(a, b)
+        d, hop, schur = res[1, 0]
         for k in range(2):
             assert rel(d[k], orc.D(psi[k])) <= TOL[prec]
         assert rel(hop, orc.hop(psi[0])) <= TOL[prec]
