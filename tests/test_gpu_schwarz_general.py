@@ -1,7 +1,7 @@
 """Schwarz block solves with the block vectors in device memory: explicit
 cores (8 x 4 x 4 x 8 and others), overlap 2, and the BiCGStab block solver,
-against the FP64 oracle's RAS with the same recipe (the survey's NEXT-3
-variants; the paper leaves the Schwarz recipe open).  The same path at the
+against the FP64 oracle's RAS with the same recipe (the paper leaves the
+Schwarz recipe open, Sec. 2).  The same path at the
 fused kernel's settings must agree with the fused kernel.  FP32 block
 arithmetic: 1e-5 relative (FP16 links and clover: 3e-3)."""
 import numpy as np
