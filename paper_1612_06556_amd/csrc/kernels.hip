@@ -224,61 +224,6 @@ WCL_D M3 link_at(const Geom &g, const void *u64, const int x[4], const int d[4],
     return m;
 }
 
-// Traceless F_{mu nu}(x) from the clover leaves.
-WCL_D M3 field_strength(const Geom &g, const void *u64, const int x[4], int mu, int nu)
-{
-    int o[4] = {0, 0, 0, 0};
-    int pm[4] = {0, 0, 0, 0}, pn[4] = {0, 0, 0, 0}, mm[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
-    int mmpn[4] = {0, 0, 0, 0}, mmmn[4] = {0, 0, 0, 0}, pmmn[4] = {0, 0, 0, 0};
-    pm[mu] = 1; pn[nu] = 1; mm[mu] = -1; mn[nu] = -1;
-    mmpn[mu] = -1; mmpn[nu] = 1;
-    mmmn[mu] = -1; mmmn[nu] = -1;
-    pmmn[mu] = 1; pmmn[nu] = -1;
-    // the two links at x are shared by leaves 1 and 4 / 1 and 2
-    const M3 Umu = link_at(g, u64, x, o, mu), Unu = link_at(g, u64, x, o, nu);
-    // leaf 1: x -> x+mu -> x+mu+nu -> x+nu -> x
-    M3 Q = m3_mul(m3_mul(Umu, link_at(g, u64, x, pm, nu)),
-                  m3_mul(m3_dag(link_at(g, u64, x, pn, mu)), m3_dag(Unu)));
-    // leaf 2: x -> x+nu -> x-mu+nu -> x-mu -> x
-    {
-        const M3 a = m3_mul(Unu, m3_dag(link_at(g, u64, x, mmpn, mu)));
-        const M3 b = m3_mul(m3_dag(link_at(g, u64, x, mm, nu)), link_at(g, u64, x, mm, mu));
-        const M3 l = m3_mul(a, b);
-#pragma unroll
-        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
-    }
-    // leaf 3: x -> x-mu -> x-mu-nu -> x-nu -> x
-    {
-        const M3 a = m3_mul(m3_dag(link_at(g, u64, x, mm, mu)), m3_dag(link_at(g, u64, x, mmmn, nu)));
-        const M3 b = m3_mul(link_at(g, u64, x, mmmn, mu), link_at(g, u64, x, mn, nu));
-        const M3 l = m3_mul(a, b);
-#pragma unroll
-        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
-    }
-    // leaf 4: x -> x-nu -> x+mu-nu -> x+mu -> x
-    {
-        const M3 a = m3_mul(m3_dag(link_at(g, u64, x, mn, nu)), link_at(g, u64, x, mn, mu));
-        const M3 b = m3_mul(link_at(g, u64, x, pmmn, nu), m3_dag(Umu));
-        const M3 l = m3_mul(a, b);
-#pragma unroll
-        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + l.a[k];
-    }
-    // F = (Q - Q^dag) / (8 i), then remove the trace
-    M3 F;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const double wr = Q.a[i * 3 + j].re - Q.a[j * 3 + i].re;
-            const double wi = Q.a[i * 3 + j].im + Q.a[j * 3 + i].im;
-            F.a[i * 3 + j] = {wi * 0.125, -wr * 0.125};
-        }
-    const double tr = (F.a[0].re + F.a[4].re + F.a[8].re) / 3.0;
-    F.a[0].re -= tr; F.a[4].re -= tr; F.a[8].re -= tr;
-    F.a[0].im = F.a[4].im = F.a[8].im = 0.0;
-    return F;
-}
-
 // Inverse of a Hermitian positive definite 6x6 by Cholesky: A = L L^dag,
 // A^-1 = W^dag W with W = L^-1.  Returns false on a non-positive pivot.
 WCL_D bool hpd_inverse6(const cplx<double> A[36], cplx<double> Ai[36])
@@ -348,27 +293,80 @@ WCL_D void pack_block(const cplx<double> A[36], double *out36)
         }
 }
 
-// Clover setup in two passes.  Pass 1: one thread per (site, plane) forms the
-// traceless Hermitian F_{mu nu} and stores its upper triangle (F00, F11, F22,
+// One clover leaf of plane (mu, nu) at x (leaf 0: x -> x+mu -> x+mu+nu ->
+// x+nu; 1: x -> x+nu -> x-mu+nu -> x-mu; 2: x -> x-mu -> x-mu-nu -> x-nu;
+// 3: x -> x-nu -> x+mu-nu -> x+mu; each back to x).
+WCL_D M3 clover_leaf(const Geom &g, const void *u64, const int x[4], int mu, int nu, int leaf)
+{
+    int o[4] = {0, 0, 0, 0};
+    int pm[4] = {0, 0, 0, 0}, pn[4] = {0, 0, 0, 0}, mm[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
+    int mmpn[4] = {0, 0, 0, 0}, mmmn[4] = {0, 0, 0, 0}, pmmn[4] = {0, 0, 0, 0};
+    pm[mu] = 1; pn[nu] = 1; mm[mu] = -1; mn[nu] = -1;
+    mmpn[mu] = -1; mmpn[nu] = 1;
+    mmmn[mu] = -1; mmmn[nu] = -1;
+    pmmn[mu] = 1; pmmn[nu] = -1;
+    if (leaf == 0)
+        return m3_mul(m3_mul(link_at(g, u64, x, o, mu), link_at(g, u64, x, pm, nu)),
+                      m3_mul(m3_dag(link_at(g, u64, x, pn, mu)), m3_dag(link_at(g, u64, x, o, nu))));
+    if (leaf == 1)
+        return m3_mul(m3_mul(link_at(g, u64, x, o, nu), m3_dag(link_at(g, u64, x, mmpn, mu))),
+                      m3_mul(m3_dag(link_at(g, u64, x, mm, nu)), link_at(g, u64, x, mm, mu)));
+    if (leaf == 2)
+        return m3_mul(m3_mul(m3_dag(link_at(g, u64, x, mm, mu)), m3_dag(link_at(g, u64, x, mmmn, nu))),
+                      m3_mul(link_at(g, u64, x, mmmn, mu), link_at(g, u64, x, mn, nu)));
+    return m3_mul(m3_mul(m3_dag(link_at(g, u64, x, mn, nu)), link_at(g, u64, x, mn, mu)),
+                  m3_mul(link_at(g, u64, x, pmmn, nu), m3_dag(link_at(g, u64, x, o, mu))));
+}
+
+// Clover setup in two passes.  Pass 1: a workgroup takes 64 sites of one
+// plane, each wave one of the four leaves; the leaves meet in LDS and the
+// first wave forms the traceless Hermitian F_{mu nu} = (Q - Q^dag)/(8i) - tr
+// (Q = leaf 0 + 1 + 2 + 3) and stores its upper triangle (F00, F11, F22,
 // Re/Im F01, F02, F12: 9 reals) in F[plane][9][2 Vh].  Planes: E_k = F_{k t}
 // (0..2), B_x = F_yz, -B_y = F_xz, B_z = F_xy (3..5).
-__global__ void __launch_bounds__(128) k_clover_fs(Geom g, const void *u64, double *F)
+__global__ void __launch_bounds__(256) k_clover_fs(Geom g, const void *u64, double *F)
 {
+    __shared__ double lq[4][18][64];
     const int n = 2 * g.Vh;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+    const int lane = threadIdx.x & 63, leaf = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + lane;
     const int plane = blockIdx.y;
-    const int p = idx / g.Vh;
-    const int h = idx - p * g.Vh;
-    const Site s = decompose(g, h, p);
     // (mu, nu) of the planes: (0,3) (1,3) (2,3) (1,2) (0,2) (0,1)
     const int mu = plane < 3 ? plane : (plane == 3 ? 1 : 0);
     const int nu = plane < 3 ? 3 : (plane == 5 ? 1 : 2);
-    const M3 f = field_strength(g, u64, s.x, mu, nu);
+    if (idx < n) {
+        const int p = idx / g.Vh;
+        const Site s = decompose(g, idx - p * g.Vh, p);
+        const M3 l = clover_leaf(g, u64, s.x, mu, nu, leaf);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            lq[leaf][2 * k][lane] = l.a[k].re;
+            lq[leaf][2 * k + 1][lane] = l.a[k].im;
+        }
+    }
+    __syncthreads();
+    if (leaf != 0 || idx >= n) return;
+    M3 Q;
+#pragma unroll
+    for (int k = 0; k < 9; k++) Q.a[k] = {lq[0][2 * k][lane], lq[0][2 * k + 1][lane]};
+#pragma unroll
+    for (int q = 1; q < 4; q++)
+#pragma unroll
+        for (int k = 0; k < 9; k++) Q.a[k] = Q.a[k] + cplx<double>{lq[q][2 * k][lane], lq[q][2 * k + 1][lane]};
+    M3 f;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double wr = Q.a[i * 3 + j].re - Q.a[j * 3 + i].re;
+            const double wi = Q.a[i * 3 + j].im + Q.a[j * 3 + i].im;
+            f.a[i * 3 + j] = {wi * 0.125, -wr * 0.125};
+        }
+    const double tr = (f.a[0].re + f.a[4].re + f.a[8].re) / 3.0;
     double *o = F + (size_t)plane * 9 * n + idx;
-    o[0] = f.a[0].re;
-    o[(size_t)n] = f.a[4].re;
-    o[2 * (size_t)n] = f.a[8].re;
+    o[0] = f.a[0].re - tr;
+    o[(size_t)n] = f.a[4].re - tr;
+    o[2 * (size_t)n] = f.a[8].re - tr;
     o[3 * (size_t)n] = f.a[1].re;
     o[4 * (size_t)n] = f.a[1].im;
     o[5 * (size_t)n] = f.a[2].re;
@@ -473,7 +471,7 @@ hipError_t launch_clover_build(const Geom &g, const void *u64, double ck, void *
                                void *ti32, void *t16, void *ti16, int *info, double *fbuf, hipStream_t st)
 {
     const int n = 2 * g.Vh;
-    k_clover_fs<<<dim3((n + 127) / 128, 6), 128, 0, st>>>(g, u64, fbuf);
+    k_clover_fs<<<dim3((n + 63) / 64, 6), 256, 0, st>>>(g, u64, fbuf);
     k_clover_inv<<<(n + 63) / 64, 64, 0, st>>>(g, fbuf, ck, t64, ti64, t32, ti32, t16, ti16, info);
     return hipGetLastError();
 }
