@@ -82,7 +82,7 @@ def parse():
 def cpu_baseline(U, psi, budget_s=12.0):
     """The FP64 oracle on the host cores (bounded samples): the full-lattice D
     apply at 24^3x32 on all cores and on one thread, the hopping term alone,
-    and a plain FP64 BiCGStab solve at 8^4."""
+    and plain FP64 BiCGStab solves at 8^4 and 16^3x32."""
     import oracle
     from paper_1612_06556_amd import synth
     V = int(np.prod(DIMS))
@@ -110,11 +110,18 @@ def cpu_baseline(U, psi, budget_s=12.0):
     t0 = time.perf_counter()
     _, info = o8.bicgstab_full(synth.gaussian_spinor(d8, 2001), 1e-10, 10000)
     t8 = time.perf_counter() - t0
+    d16 = (16, 16, 16, 32)
+    o16 = oracle.Oracle(d16, -1, 0.125, CSW, synth.su3_field(d16, 1002))
+    t0 = time.perf_counter()
+    _, info16 = o16.bicgstab_full(synth.gaussian_spinor(d16, 2002), 1e-10, 10000)
+    t16 = time.perf_counter() - t0
     return {"value": round(flops / el / 1e9, 3), "unit": "GFlop/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} full-lattice FP64 D applications at 24^3x32 (1872 flop/site), {el:.1f} s",
             "single_thread_value": round(n1 * V * 1872.0 / el1 / 1e9, 3),
             "hop_value": round(nh * V * 1320.0 / elh / 1e9, 3),
-            "plain_fp64_8x8x8x8": {"ms": round(t8 * 1e3, 1), "iters": info["iters"], "relres": info["relres"]}}
+            "plain_fp64_8x8x8x8": {"ms": round(t8 * 1e3, 1), "iters": info["iters"], "relres": info["relres"]},
+            "plain_fp64_16x16x16x32": {"ms": round(t16 * 1e3, 1), "iters": info16["iters"],
+                                       "relres": info16["relres"]}}
 
 
 def _median_ms(fn, trials=5):
