@@ -166,3 +166,22 @@ def test_general_schwarz_refusals():
     with pytest.raises(wcl.WclError):
         lat.set_ras_cores((4, 4, 4, 4))  # explicit cores while multiplicative
     lat.close()
+
+
+@pytest.mark.parametrize("opts", [dict(ras_solver=2, ras_iters=2), dict(ras_overlap=2)],
+                         ids=["bicgstab", "overlap2"])
+def test_general_schwarz_graph_replay(opts):
+    """The device-memory block solves inside a captured inner iteration
+    (kernels only, block fields cleared by a kernel, no memset nodes): every
+    replay of a multi-iteration solve, twice in a row, gives bitwise the
+    eagerly launched solution, for two right-hand sides."""
+    dims = (8, 8, 8, 8)
+    lat, _ = _lattice(dims, 1001, kappa=0.12, compress=True)
+    b = to_gpu(synth.gaussian_spinor(dims, 2001, nrhs=2))
+    x0, i0, rc0 = lat.solve(b, tol=1e-10, use_graph=0, **opts)
+    for _ in range(2):
+        x1, i1, rc1 = lat.solve(b, tol=1e-10, use_graph=1, **opts)
+        assert rc0 == 0 and rc1 == 0
+        assert np.array_equal(to_host(x0), to_host(x1))
+        assert [i["inner_iters_total"] for i in i0] == [i["inner_iters_total"] for i in i1]
+    lat.close()
