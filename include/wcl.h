@@ -60,23 +60,36 @@ enum {
 /* Storage precision of links, clover and vectors in wcl_apply / wcl_apply_op. */
 enum { WCL_PREC64 = 64, WCL_PREC32 = 32, WCL_PREC16 = 16 };
 
-/* Create a context for one lattice on the current HIP device.
+/* Create a context for one lattice on the current HIP device (the paper's
+ * solver holds its gauge and clover fields resident on the card between
+ * calls, Sec. 2; here that state is explicit and owned by the context).
  * tile: extents of the internal blocked layout and of the Schwarz cores
  * (each even and dividing dims[mu]); NULL picks 4^4 when it divides the
  * lattice, else 2^4.  t_bc = +1 periodic, -1 antiperiodic in time.
  * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
- * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL. */
+ * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL;
+ * WCL_ENOMEM / WCL_EHIP when the context's first device buffers fail. */
 int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream, wcl_ctx **out);
+/* Switch the stream every later call of this context is ordered on. */
 int wcl_set_stream(wcl_ctx *ctx, void *hip_stream);
-/* Copy and convert the gauge field (FP64, FP32 and FP16 internal copies). */
+/* Copy and convert the gauge field U (the links of the Wilson-Clover matrix,
+ * Sec. 1) into the context's FP64, FP32 and FP16 copies in the blocked
+ * even/odd layout; the caller's buffer is read on the stream and not kept.
+ * Invalidates kappa / c_sw (call wcl_set_params again).  Errors:
+ * WCL_EINVAL (null), WCL_ENOMEM, WCL_EHIP, and with two-row storage on the
+ * SU(3) check below. */
 int wcl_set_gauge(wcl_ctx *ctx, const double *U_dev);
-/* Set kappa and c_sw; (re)builds T and T^-1 per site in FP64 (then stored in
- * FP64, FP32 and FP16).  WCL_ESTATE before wcl_set_gauge; WCL_ENAN if a
- * clover block is not positive definite. */
+/* Set kappa and c_sw of the Wilson-Clover matrix (Sec. 1; kappa is also an
+ * argument of the paper's offloaded solver, Sec. 2); (re)builds the clover
+ * term T and T^-1 per site in FP64 (then stored in FP64, FP32 and FP16), the
+ * blocks the even/odd preconditioning divides by.  Synchronises the stream.
+ * WCL_ESTATE before wcl_set_gauge; WCL_EINVAL for non-finite values;
+ * WCL_ENAN if a clover block is not positive definite. */
 int wcl_set_params(wcl_ctx *ctx, double kappa, double csw);
 
 /* Two-row (12-real) link storage for the FP32 and FP16 tiers (enable 1) or
- * full 3x3 links (0, the default).  An SU(3) matrix is fixed by its first two
+ * full 3x3 links (0, the default): the SU(3) reconstruction the paper's
+ * single-precision solver uses (Sec. 2; it keeps two columns, here two rows).  An SU(3) matrix is fixed by its first two
  * rows (row 2 = conj(row0 x row1)), so the hopping and Schwarz kernels read
  * 48 (FP32) or 24 (FP16) bytes per link instead of 72 / 36 and rebuild the
  * third row in registers; FP64 work always uses the full links.  Enabling
@@ -88,12 +101,20 @@ int wcl_set_params(wcl_ctx *ctx, double kappa, double csw);
 int wcl_set_compression(wcl_ctx *ctx, int enable);
 
 /* out = D in (dagger = 0) or D^dag in (dagger = 1) on nrhs full-lattice
- * spinors, computed with links, clover and vectors stored in prec
- * (64, 32: FP32 storage and arithmetic, 16: FP16 storage, FP32 arithmetic).
- * in_dev and out_dev must not overlap. */
+ * spinors: the Wilson-Clover quark matrix whose hopping part is the paper's
+ * measured "MULT" kernel (Sec. 2, Sec. 3).  Computed with links, clover and
+ * vectors stored in prec (64; 32: FP32 storage and arithmetic; 16: FP16
+ * storage, FP32 arithmetic).  in_dev / out_dev: complex128
+ * [nrhs][V][4][3] device buffers owned by the caller; they must not
+ * overlap.  WCL_ESTATE before wcl_set_params; WCL_EINVAL for nrhs < 1, an
+ * unknown prec or a null pointer; WCL_ENOMEM when the context's workspace
+ * cannot grow (it is allocated on first use and kept). */
 int wcl_apply(wcl_ctx *ctx, const double *in_dev, double *out_dev, int nrhs, int dagger, int prec);
 
-/* One step of the hot path on canonical FP64 vectors, for per-step checks:
+/* One step of the hot path on canonical FP64 vectors, for per-step checks of
+ * the even/odd preconditioned matrix and its RAS preconditioner (Sec. 2);
+ * same buffer rules and errors as wcl_apply, and WCL_EINVAL for an unknown
+ * op, RAS at prec 64 and SCHUR_RHS below prec 64:
  *   WCL_OP_HOP        out = H in                      (both parities)
  *   WCL_OP_CLOVER     out = T in
  *   WCL_OP_CLOVER_INV out = T^-1 in
@@ -155,6 +176,14 @@ typedef struct {
     int inner_vec_prec;  /* 32, or 16: the inner solver's vectors stored in FP16 (FP32
                           * arithmetic; needs inner_prec 16)                        */
     int ras_mult;        /* 1: multiplicative Schwarz (colour sweeps), see wcl_set_ras */
+    int persistent;      /* 1: each inner solve runs as one persistent cooperative kernel
+                          * (every inner iteration, reductions and convergence test on
+                          * the device; FBICGSTAB / DC, additive Schwarz on the fused
+                          * kernel or no Schwarz, one or more right-hand sides)      */
+    const double *x0_dev; /* NULL: zero start.  Else an initial guess, complex128
+                          * [nrhs][V][4][3] on the device (the paper's solver takes the
+                          * solution vector in and out, Sec. 2); its even sites start
+                          * the even/odd solvers, the whole field the full-D solver */
 } wcl_solve_opts;
 
 typedef struct {
@@ -168,38 +197,56 @@ typedef struct {
 
 /* Fill opts with the defaults: tol 1e-10, FBICGSTAB, RAS on (overlap 1,
  * 4 iterations, minimal residual), inner_tol 1e-2, FP32 inner links and
- * vectors, 100 outer, 500 inner. */
+ * vectors, 100 outer, 500 inner, zero start, launch-per-kernel inner solve. */
 void wcl_default_opts(wcl_solve_opts *opts);
 
-/* Solve D x = b for nrhs right-hand sides (one after another, sharing the
- * context's workspace).  x_dev is written (zero start).  info (nrhs
- * entries, may be NULL) receives per-rhs results.  Returns the worst status. */
+/* Solve D x = b (the quark propagator, Sec. 1) for nrhs right-hand sides by
+ * the paper's FP64 flexible BiCGStab over the single-precision BiCGStab with
+ * even/odd and overlapped RAS preconditioning (Sec. 2), or by the variants
+ * selected in opts.  All right-hand sides advance in lockstep through the
+ * same launches (per-rhs scalars; a converged right-hand side is masked out).
+ * b_dev, x_dev: complex128 [nrhs][V][4][3], caller-owned, must not overlap;
+ * x_dev is written; opts->x0_dev (may alias x_dev) is the initial guess or
+ * NULL for zero.  info (nrhs entries, may be NULL) receives per-rhs results.
+ * Returns the worst status: WCL_ENOCONV (x holds the best iterate),
+ * WCL_EBREAKDOWN (BiCGStab broke down on the last restart allowed), WCL_ENAN,
+ * WCL_EINVAL for bad options, WCL_ESTATE before wcl_set_params. */
 int wcl_solve(wcl_ctx *ctx, const double *b_dev, double *x_dev, int nrhs, const wcl_solve_opts *opts,
               wcl_solve_info *info);
 
-/* Gradient of L = Re<eta, D^-1 b> from x = D^-1 b and y = D^-dag eta (both
- * canonical FP64 device spinors): gU_dev[V][4][3][3] complex128 receives
- * 2 dL/d conj(U) (PyTorch's convention), *gkappa_host dL/dkappa. */
+/* Not in the paper: the differentiation workload this library adds around
+ * the solve.  Gradient of L = Re<eta, D^-1 b> from x = D^-1 b and
+ * y = D^-dag eta (both canonical FP64 device spinors, caller-owned):
+ * gU_dev[V][4][3][3] complex128 receives 2 dL/d conj(U) (PyTorch's
+ * convention), *gkappa_host dL/dkappa.  Synchronises the stream.
+ * WCL_ESTATE before wcl_set_params; WCL_EINVAL for null pointers. */
 int wcl_grad(wcl_ctx *ctx, const double *x_dev, const double *y_dev, double *gU_dev, double *gkappa_host);
 
-/* Time the standalone even/odd hopping kernel H_eo (FP32 or FP16 links, two-row
- * when compression is on; FP32 spinors):
- * `reps` launches after 10 warm-ups, rotating over `copies` independent sets
- * of links and spinors (copies >= 1; more copies defeat the 256 MB Infinity
- * Cache).  *ms_per_call receives the mean launch time from HIP events. */
-int wcl_bench_hop(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
+/* Time the standalone even/odd hopping kernel H_eo, the paper's measured
+ * "MULT" (Sec. 3), on nrhs right-hand sides per launch (FP32 or FP16 links,
+ * two-row when compression is on; FP32 spinors; nrhs > 1 uses the batched
+ * launch shape of wcl_set_batch_tuning): `reps` launches after 10 warm-ups,
+ * rotating over `copies` independent sets of links and spinors (1 <= copies
+ * <= 32; more copies defeat the 256 MB Infinity Cache).  *ms_per_call
+ * receives the mean launch time from HIP events.  Buffers come from the
+ * context's workspace.  WCL_ESTATE before wcl_set_gauge; WCL_EINVAL for
+ * other precisions, nrhs outside 1..64 or bad counts. */
+int wcl_bench_hop(wcl_ctx *ctx, int prec, int nrhs, int reps, int copies, double *ms_per_call);
 /* Time the standalone clover apply out_e = T_ee^-1 in_e (FP32 or FP16
- * clover, FP32 spinors), the 504-flop-per-site half of the Schur operator,
- * with the same protocol.  WCL_ESTATE before wcl_set_params. */
+ * clover, FP32 spinors), the 504-flop-per-site part of the even/odd
+ * preconditioned matrix (Sec. 2), with the protocol of wcl_bench_hop for
+ * one right-hand side.  WCL_ESTATE before wcl_set_params. */
 int wcl_bench_clover(wcl_ctx *ctx, int prec, int reps, int copies, double *ms_per_call);
 
-/* Streaming ceilings of the device, for the roofline: the mean rate of a
+/* Not in the paper (measurement): streaming ceilings of the device, for the
+ * roofline: the mean rate of a
  * read-only pass and of a copy over two buffers of `mib` MiB each (context
  * workspace; `reps` launches after 10 warm-ups).  *read_gbs = bytes read per
  * second, *copy_gbs = bytes read + written per second, in GB/s. */
 int wcl_bench_stream(wcl_ctx *ctx, double mib, int reps, double *read_gbs, double *copy_gbs);
 
-/* Kernel-class profiling on the context's stream: with profiling enabled,
+/* Not in the paper (measurement): kernel-class profiling on the context's
+ * stream: with profiling enabled,
  * every launch of the classes below is timed by HIP events (carried in the
  * kernel's dispatch packet for the single-kernel hop, RAS and clover
  * launches; recorded around multi-kernel launches) and its
@@ -224,7 +271,9 @@ int wcl_profile_read(wcl_ctx *ctx, int kclass, wcl_kstat *out);
  * (launches, bytes, flops) with ms = 0.  WCL_EINVAL for other bits. */
 int wcl_profile_mask(wcl_ctx *ctx, int mask);
 
-/* Launch configuration of the hopping kernel: threads per workgroup (64, 128,
+/* Not in the paper (tuning; the paper tunes its KNC kernel by loop blocking
+ * and prefetching, Sec. 2).  Launch configuration of the hopping kernel:
+ * threads per workgroup (64, 128,
  * 256), pipeline depth (2, 3: hops of a site whose neighbour spinor and
  * link are in flight while an earlier hop is computed), XCD-aware workgroup
  * order (0/1) and non-temporal link/clover loads (0/1; single right-hand
@@ -237,8 +286,8 @@ int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
  * copies the input spinors of its own half-sites into LDS and reads the
  * neighbours that fall in that range from there (in the blocked layout most
  * of a tile's hops stay inside the tile), the rest from global memory.
- * Applies to depth-2, non-dagger, temporal-load launches; results are
- * bitwise those of the unstaged kernel.  enable = 0 switches it off. */
+ * Applies to depth-2, non-dagger launches (temporal or non-temporal operator
+ * loads); results are bitwise those of the unstaged kernel.  enable = 0 switches it off. */
 int wcl_set_hop_staging(wcl_ctx *ctx, int enable);
 /* Batched launches (nrhs > 1) of the FP32-vector hopping kernels (the inner
  * solver's Schur halves): rhs_per_thread = 1 gives each right-hand side its
@@ -247,7 +296,11 @@ int wcl_set_hop_staging(wcl_ctx *ctx, int enable);
  * serves all of them.  WCL_EINVAL for other values. */
 int wcl_set_batch_tuning(wcl_ctx *ctx, int rhs_per_thread);
 
+/* Message of the last failure on the calling thread (never NULL; owned by
+ * the library, valid until the thread's next failing call). */
 const char *wcl_last_error(void);
+/* Synchronise the context's stream and free every device buffer it owns;
+ * NULL is accepted.  Always WCL_OK. */
 int wcl_destroy(wcl_ctx *ctx);
 
 #ifdef __cplusplus

@@ -706,7 +706,11 @@ int wcl_set_ras(wcl_ctx *c, int overlap, int iters, int solver, int multiplicati
                                 "solver and an extended block of at most 648 sites per parity");
     }
     c->ras_mult = multiplicative;
-    return ensure_gras(c);
+    const int rc = ensure_gras(c);
+    if (rc != WCL_OK) {
+        c->ras_overlap = o0; c->ras_iters = i0; c->ras_solver = s0; c->ras_mult = m0;
+    }
+    return rc;
 }
 
 int wcl_set_ras_cores(wcl_ctx *c, const int cores[4])
@@ -722,8 +726,15 @@ int wcl_set_ras_cores(wcl_ctx *c, const int cores[4])
         }
         if (c->ras_mult) return fail(WCL_EINVAL, "explicit cores run the additive Schwarz only");
     }
-    for (int mu = 0; mu < 4; mu++) c->ras_cores[mu] = nc[mu];
-    return ensure_gras(c);
+    int old[4];
+    for (int mu = 0; mu < 4; mu++) {
+        old[mu] = c->ras_cores[mu];
+        c->ras_cores[mu] = nc[mu];
+    }
+    const int rc = ensure_gras(c);
+    if (rc != WCL_OK)
+        for (int mu = 0; mu < 4; mu++) c->ras_cores[mu] = old[mu];
+    return rc;
 }
 
 int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, int prec)
@@ -1085,6 +1096,7 @@ struct Driver {
     bool flex;      // right preconditioned by the inner solve
     size_t m;       // complex numbers per right-hand side
     void *x, *bvec;
+    bool warm;      // w.x holds the initial guess (full fields), else zero start
 };
 
 int apply_A(wcl_ctx *c, const Driver &d, SolveWs &w, const void *in, void *out, const Scalars *sc)
@@ -1129,20 +1141,52 @@ int restart(wcl_ctx *c, const Driver &d, SolveWs &w, int k, double tol, const st
     return WCL_OK;
 }
 
+// Initial iterate and residual r = bvec - A x of a driver.  Zero start: x = 0,
+// r = bvec.  Warm start: x = the guess held in the full fields w.x (its even
+// halves for the even/odd systems); a right-hand side whose guess already
+// meets the tolerance (true residual of the full system) is final at once.
+int initial_residual(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, SolveWs &w,
+                     const std::vector<double> &bnorm2, std::vector<int> &final_, std::vector<wcl_solve_info> &info)
+{
+    const int n = w.n;
+    const size_t m = d.m;
+    if (!d.warm) {
+        HIPCHK(launch_copy(P64, n * m, d.bvec, w.r, c->st));
+        HIPCHK(launch_zero(P64, n * m, d.x, c->st));
+        return WCL_OK;
+    }
+    if (d.eo) {
+        for (int k = 0; k < n; k++)
+            HIPCHK(hipMemcpyAsync((char *)d.x + k * half_bytes(P64, c->Vh), (char *)w.x + k * full_bytes(P64, c->Vh),
+                                  half_bytes(P64, c->Vh), hipMemcpyDeviceToDevice, c->st));
+    }
+    std::vector<double> rel(n, 0.0);
+    CHK(check_true(c, d, w, bnorm2, rel));
+    for (int k = 0; k < n; k++) {
+        if (final_[k]) continue;
+        info[k].true_relres = rel[k];
+        if (rel[k] <= o.tol) { final_[k] = 1; info[k].status = WCL_OK; }
+    }
+    CHK(apply_A(c, d, w, d.x, w.t, nullptr));
+    HIPCHK(launch_copy(P64, n * m, d.bvec, w.r, c->st));
+    HIPCHK(launch_axpby(P64, n * m, make_double2(-1.0, 0.0), w.t, make_double2(1.0, 0.0), w.r, c->st));
+    return WCL_OK;
+}
+
 int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const InnerCfg *cfg, SolveWs &w,
                     const std::vector<double> &bnorm2, std::vector<int> &final_, std::vector<wcl_solve_info> &info)
 {
     const int n = w.n;
     const size_t m = d.m;
     Scalars *sc = SO(c);
-    HIPCHK(launch_copy(P64, n * m, d.bvec, w.r, c->st));
-    HIPCHK(launch_zero(P64, n * m, d.x, c->st));
+    CHK(initial_residual(c, d, o, w, bnorm2, final_, info));
     CHK(write_final(c, final_));
     CHK(restart(c, d, w, -1, o.tol, bnorm2));
     for (int k = 0; k < n; k++)
         if (!final_[k] && HO(c)[k].b2 == 0.0) { final_[k] = 1; info[k].status = WCL_OK; }
     std::vector<int> it_inner(n, 0);
     std::vector<int> restarts(n, 0);
+    std::vector<int> broke(n, 0);   // the last stop of the recurrence was a breakdown
     for (int k = 0; k < n; k++) info[k].outer_iters = 0;
     int iter = 0;
     const int every = d.flex ? 1 : std::max(1, o.check_every);
@@ -1195,6 +1239,7 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
             exec = std::max(exec, HO(c)[k].iter - info[k].outer_iters);
             info[k].outer_iters = HO(c)[k].iter;
             if (!std::isfinite(HO(c)[k].r2)) { final_[k] = 1; info[k].status = WCL_ENAN; continue; }
+            broke[k] = HO(c)[k].done == 2;
             if (HO(c)[k].done) candidates = true;
         }
         for (size_t q = (size_t)std::max(exec, 0); q < rec_mark.size(); q++) {  // queued after convergence
@@ -1209,7 +1254,7 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
             if (final_[k] || !HO(c)[k].done) continue;
             info[k].true_relres = rel[k];
             if (rel[k] <= o.tol) { final_[k] = 1; info[k].status = WCL_OK; continue; }
-            if (restarts[k] >= 8) { final_[k] = 1; info[k].status = WCL_ENOCONV; continue; }
+            if (restarts[k] >= 8) { final_[k] = 1; info[k].status = broke[k] ? WCL_EBREAKDOWN : WCL_ENOCONV; continue; }
             restarts[k]++;
             any_restart = true;
         }
@@ -1230,8 +1275,9 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
             }
         }
     }
+    // out of iterations: a recurrence that ended in a breakdown reports it
     for (int k = 0; k < n; k++)
-        if (!final_[k]) info[k].status = WCL_ENOCONV;
+        if (!final_[k]) info[k].status = broke[k] ? WCL_EBREAKDOWN : WCL_ENOCONV;
     return WCL_OK;
 }
 
@@ -1241,10 +1287,9 @@ int outer_dc(wcl_ctx *c, const wcl_solve_opts &o, const InnerCfg &cfg, SolveWs &
 {
     const int n = w.n;
     const size_t m = 12 * (size_t)c->Vh;
-    HIPCHK(launch_copy(P64, n * m, w.bh, w.r, c->st));
-    HIPCHK(launch_zero(P64, n * m, w.xe, c->st));
     std::vector<int> it(n, 0);
-    Driver d{true, true, m, w.xe, w.bh};
+    Driver d{true, true, m, w.xe, w.bh, o.x0_dev != nullptr};
+    CHK(initial_residual(c, d, o, w, bnorm2, final_, info));
     for (int outer = 0; outer < o.max_outer; outer++) {
         bool any_active = false;
         for (int k = 0; k < n; k++) any_active = any_active || !final_[k];
@@ -1298,6 +1343,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     if (o.inner_vec_prec == 16 && o.inner_prec != 16)
         return fail(WCL_EINVAL, "FP16 inner vectors need the FP16 links and clover (inner_prec 16)");
     if (o.check_every < 1) o.check_every = 8;
+    if (o.persistent) return fail(WCL_EINVAL, "persistent inner solve not available");
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
     const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
     const bool inner = !plain && !plain_eo;
@@ -1332,6 +1378,14 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     for (int k = 0; k < n; k++)
         HIPCHK(launch_pack_spinor(c->g, b + (size_t)k * c->V * 24, (char *)w.b + k * fb, c->st));
     if (o.adjoint) HIPCHK(launch_gamma5(2 * (size_t)n, c->Vh, w.b, c->st));  // D^dag = g5 D g5
+    // initial guess (may alias x): the solve of D x' = g5 b starts from g5 x0
+    // when adjoint
+    const bool warm = o.x0_dev != nullptr;
+    if (warm) {
+        for (int k = 0; k < n; k++)
+            HIPCHK(launch_pack_spinor(c->g, o.x0_dev + (size_t)k * c->V * 24, (char *)w.x + k * fb, c->st));
+        if (o.adjoint) HIPCHK(launch_gamma5(2 * (size_t)n, c->Vh, w.x, c->st));
+    }
     std::vector<double> bnorm2(n);
     CHK(norms_host(c, P64, 24 * (size_t)c->Vh, w.b, 24 * (size_t)c->Vh, n, bnorm2.data()));
     std::vector<wcl_solve_info> info(n);
@@ -1342,15 +1396,15 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         else if (bnorm2[k] == 0.0) { final_[k] = 1; info[k].status = WCL_OK; }
     }
     if (plain) {
-        Driver d{false, false, 24 * (size_t)c->Vh, w.x, w.b};
+        Driver d{false, false, 24 * (size_t)c->Vh, w.x, w.b, warm};
         CHK(bicgstab_driver(c, d, o, nullptr, w, bnorm2, final_, info));
     } else {
         CHK(schur_rhs64(c, w.b, w.bh, w.o, w.s, n));
         if (plain_eo) {
-            Driver d{true, false, 12 * (size_t)c->Vh, w.xe, w.bh};
+            Driver d{true, false, 12 * (size_t)c->Vh, w.xe, w.bh, warm};
             CHK(bicgstab_driver(c, d, o, nullptr, w, bnorm2, final_, info));
         } else if (o.outer == WCL_OUTER_FBICGSTAB) {
-            Driver d{true, true, 12 * (size_t)c->Vh, w.xe, w.bh};
+            Driver d{true, true, 12 * (size_t)c->Vh, w.xe, w.bh, warm};
             CHK(bicgstab_driver(c, d, o, &cfg, w, bnorm2, final_, info));
         } else {
             CHK(outer_dc(c, o, cfg, w, bnorm2, final_, info));
@@ -1382,7 +1436,11 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     for (int k = 0; k < n; k++) {
         info[k].seconds = secs;
         if (infos) infos[k] = info[k];
-        if (info[k].status != WCL_OK && (worst == WCL_OK || info[k].status == WCL_ENAN)) worst = info[k].status;
+        // worst status: NaN, then breakdown, then no convergence
+        const int rank_new = info[k].status == WCL_ENAN ? 3 : info[k].status == WCL_EBREAKDOWN ? 2
+                             : info[k].status != WCL_OK ? 1 : 0;
+        const int rank_old = worst == WCL_ENAN ? 3 : worst == WCL_EBREAKDOWN ? 2 : worst != WCL_OK ? 1 : 0;
+        if (rank_new > rank_old) worst = info[k].status;
     }
     if (worst != WCL_OK) {
         const char *what = worst == WCL_ENOCONV ? "solver did not reach the tolerance"
@@ -1426,9 +1484,10 @@ int bench_args(wcl_ctx *c, int prec, int reps, int copies, const double *ms, boo
 }
 }  // namespace
 
-extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double *ms)
+extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int nrhs, int reps, int copies, double *ms)
 {
     CHK(bench_args(c, prec, reps, copies, ms, false, "wcl_bench_hop"));
+    if (nrhs < 1 || nrhs > 64) return fail(WCL_EINVAL, "wcl_bench_hop: 1 <= nrhs <= 64 required");
     const size_t Vh = c->Vh;
     const int lb = prec_bytes(prec), ep = eff_lprec(c, prec);
     const size_t lbytes = ep == prec ? link_bytes(lb, Vh) : link_bytes_c(ep, Vh), sbytes = spinor_bytes(4, Vh);
@@ -1439,10 +1498,12 @@ extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double 
             CHK(wsget(c, S_BENCH + 3 * k, lbytes, &lk[k]));
             HIPCHK(hipMemcpyAsync(lk[k], lk[0], lbytes, hipMemcpyDeviceToDevice, c->st));
         }
-        CHK(wsget(c, S_BENCH + 3 * k + 1, sbytes, &in[k]));
-        CHK(wsget(c, S_BENCH + 3 * k + 2, sbytes, &out[k]));
+        CHK(wsget(c, S_BENCH + 3 * k + 1, sbytes * nrhs, &in[k]));
+        CHK(wsget(c, S_BENCH + 3 * k + 2, sbytes * nrhs, &out[k]));
         // deterministic, non-trivial input: copy the FP32 links' first reals
-        HIPCHK(hipMemcpyAsync(in[k], c->U32, sbytes, hipMemcpyDeviceToDevice, c->st));
+        for (int r = 0; r < nrhs; r++)
+            HIPCHK(hipMemcpyAsync((char *)in[k] + r * sbytes, (const char *)c->U32 + r * 64, sbytes,
+                                  hipMemcpyDeviceToDevice, c->st));
     }
     return time_launches(c, reps, copies, [&](int k) -> int {
         HopLaunch L = hop_base(c, prec, P32);
@@ -1451,6 +1512,8 @@ extern "C" int wcl_bench_hop(wcl_ctx *c, int prec, int reps, int copies, double 
         L.p = 0;
         L.in = in[k];
         L.out = out[k];
+        L.nrhs = nrhs;
+        L.in_stride = L.out_stride = sbytes;
         HIPCHK(launch_hop(L, c->st));
         return WCL_OK;
     }, ms);
@@ -1629,7 +1692,7 @@ extern "C" int wcl_autotune_hop(wcl_ctx *c, int prec, int copies, int *best)
             for (int io = 0; io < 2; io++) {
                 CHK(wcl_set_tuning(c, blocks[ib], depths[io], xcd, c->hop_nt));
                 double ms;
-                CHK(wcl_bench_hop(c, prec, 50, copies, &ms));
+                CHK(wcl_bench_hop(c, prec, 1, 50, copies, &ms));
                 if (ms < best_ms) { best_ms = ms; bb = blocks[ib]; bo = depths[io]; bx = xcd; }
             }
     CHK(wcl_set_tuning(c, bb, bo, bx, c->hop_nt));

@@ -36,7 +36,8 @@ class wcl_solve_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("outer", ctypes.c_int), ("use_ras", ctypes.c_int),
                 ("ras_overlap", ctypes.c_int), ("ras_iters", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int),
-                ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int), ("ras_mult", ctypes.c_int)]
+                ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int), ("ras_mult", ctypes.c_int),
+                ("persistent", ctypes.c_int), ("x0_dev", ctypes.c_void_p)]
 
 
 class wcl_solve_info(ctypes.Structure):
@@ -82,7 +83,8 @@ def load():
     lib.wcl_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(wcl_solve_opts),
                               ctypes.POINTER(wcl_solve_info)]
     lib.wcl_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
-    lib.wcl_bench_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.wcl_bench_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
     lib.wcl_bench_clover.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.wcl_destroy.argtypes = [_vp]
     lib.wcl_profile.argtypes = [_vp, ctypes.c_int]
@@ -171,9 +173,9 @@ def wcl_grad(h, x_ptr, y_ptr, gU_ptr):
     return gk.value
 
 
-def wcl_bench_hop(h, prec, reps, copies):
+def wcl_bench_hop(h, prec, reps, copies, nrhs=1):
     ms = ctypes.c_double(0.0)
-    _check(load().wcl_bench_hop(h, int(prec), int(reps), int(copies), ctypes.byref(ms)))
+    _check(load().wcl_bench_hop(h, int(prec), int(nrhs), int(reps), int(copies), ctypes.byref(ms)))
     return ms.value
 
 
@@ -299,14 +301,20 @@ class Lattice:
         """Schwarz cores (4 even extents dividing the lattice); None: the tiles."""
         wcl_set_ras_cores(self.h, cores)
 
-    def solve(self, b, raise_on_error=True, **kw):
+    def solve(self, b, raise_on_error=True, x0=None, **kw):
+        """Solve D x = b; ``x0`` (same shape as b) is an optional initial guess."""
         b, nrhs = self._spinors(b)
         x = self.torch.empty_like(b)
         o = wcl_default_opts()
         for k, v in kw.items():
-            if not hasattr(o, k):
+            if not hasattr(o, k) or k == "x0_dev":
                 raise KeyError(k)
             setattr(o, k, v)
+        if x0 is not None:
+            x0, n0 = self._spinors(x0)
+            if n0 != nrhs:
+                raise ValueError("x0 must hold one guess per right-hand side")
+            o.x0_dev = x0.data_ptr()
         self._sync_stream()
         rc, infos = wcl_solve(self.h, b.data_ptr(), x.data_ptr(), nrhs, o, raise_on_error)
         return x, (infos[0] if nrhs == 1 and b.dim() == 3 else infos), rc
@@ -319,9 +327,9 @@ class Lattice:
         gk = wcl_grad(self.h, x.data_ptr(), y.data_ptr(), gU.data_ptr())
         return gU, gk
 
-    def bench_hop(self, prec=32, reps=100, copies=1):
+    def bench_hop(self, prec=32, reps=100, copies=1, nrhs=1):
         self._sync_stream()
-        return wcl_bench_hop(self.h, prec, reps, copies)
+        return wcl_bench_hop(self.h, prec, reps, copies, nrhs)
 
     def bench_clover(self, prec=32, reps=100, copies=1):
         self._sync_stream()

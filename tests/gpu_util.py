@@ -45,3 +45,15 @@ def even_mask(dims):
     n = np.arange(int(np.prod(dims)))
     x, y, z, t = n % Lx, (n // Lx) % Ly, (n // (Lx * Ly)) % Lz, n // (Lx * Ly * Lz)
     return ((x + y + z + t) & 1) == 0
+
+
+def site_err(a, b):
+    """Largest per-site error: max over sites x of |a(x) - b(x)| divided by the
+    root-mean-square site norm of b over the sites where b is non-zero (so one
+    wrong site shows up even when the norm-wise error is small)."""
+    a = np.asarray(a).reshape(-1, 12)
+    b = np.asarray(b).reshape(-1, 12)
+    nb = np.linalg.norm(b, axis=1)
+    live = nb > 0
+    rms = float(np.sqrt(np.mean(nb[live] ** 2))) if live.any() else 1.0
+    return float(np.linalg.norm(a - b, axis=1).max() / max(rms, 1e-300))

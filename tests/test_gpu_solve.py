@@ -132,6 +132,94 @@ def test_bench_solve_24x32(inner_prec):
     lat.close()
 
 
+@pytest.mark.timeout(600)
+def test_bench_step_exact_24x32():
+    """bench.py's timed step exactly: 24^3x32, kappa 0.126, two-row links,
+    the hopping launch shape chosen by wcl_autotune_hop (FP32, 4 field
+    sets), FP64 flexible BiCGStab + FP32 RAS-BiCGStab (4^4 cores, overlap 1,
+    4 MR steps) at inner tolerance 0.1, after a fresh gauge ingest and clover
+    build: x within 1e-8 of the oracle's 1e-13 solution, per site too."""
+    import torch
+    from gpu_util import site_err
+    from paper_1612_06556_amd import wcl
+    dims = (24, 24, 24, 32)
+    U = synth.su3_field(dims, 1003)
+    lat = wcl.Lattice(dims, -1)
+    lat.set_compression(1)
+    gU = torch.from_numpy(U).cuda()
+    lat.set_gauge(gU)
+    lat.set_params(0.126, 1.0)
+    tuning = wcl.wcl_autotune_hop(lat.h, 32, 4)
+    print("autotuned", tuning, flush=True)
+    orc = oracle.Oracle(dims, -1, 0.126, 1.0, U)
+    b = synth.gaussian_spinor(dims, 2003)
+    gb = to_gpu(b)
+    opts = dict(tol=1e-10, use_ras=1, ras_overlap=1, ras_iters=4, inner_prec=32, inner_tol=1e-1,
+                outer=wcl.OUTER_FBICGSTAB)
+    for _ in range(2):   # the step re-ingests the gauge field and rebuilds the clover each time
+        lat.set_gauge(gU)
+        lat.set_params(0.126, 1.0)
+        x, info, rc = lat.solve(gb, **opts)
+    x = to_host(x)
+    print("bench step", info, flush=True)
+    assert rc == 0
+    assert _oracle_residual(orc, x, b) <= 1e-10
+    xr = _reference(orc, b, "24")
+    err, es = rel(x, xr), site_err(x, xr)
+    print(f"x error vs oracle {err:.3e}, worst site {es:.3e}", flush=True)
+    assert err <= 1e-8 and es <= 1e-7
+    lat.close()
+
+
+def test_warm_start():
+    """x0_dev: a start from the converged solution returns at once (no outer
+    iteration, status OK); a start from a perturbed solution reaches the
+    oracle's solution to 1e-8, for the flexible, defect-correction and plain
+    solvers, single and batched; x0 may alias x."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 8)
+    lat, orc, _ = setup(dims, -1, 0.12, 1.0, 1001, None)
+    b = synth.gaussian_spinor(dims, 2001)
+    xr = _reference(orc, b, "8a")
+    gb = to_gpu(b)
+    for kw in (dict(), dict(outer=wcl.OUTER_DC, inner_tol=1e-3), dict(outer=wcl.OUTER_PLAIN64, max_outer=5000),
+               dict(outer=wcl.OUTER_PLAIN64_EO, max_outer=5000), dict(adjoint=1)):
+        x, info, rc = lat.solve(gb, tol=1e-10, **kw)
+        assert rc == 0
+        x2, info2, rc2 = lat.solve(gb, tol=1e-10, x0=x, **kw)
+        print("warm from converged", kw, info2, flush=True)
+        assert rc2 == 0 and info2["outer_iters"] == 0 and info2["inner_iters_total"] == 0
+        assert info2["true_relres"] <= 1e-10
+        assert rel(to_host(x2), to_host(x)) <= 1e-12
+        pert = to_host(x) + 1e-3 * synth.gaussian_spinor(dims, 5)
+        gx = to_gpu(pert)
+        x3, info3, rc3 = lat.solve(gb, tol=1e-10, x0=gx, **kw)
+        assert rc3 == 0
+        ref = xr if not kw.get("adjoint") else None
+        if ref is not None:
+            assert rel(to_host(x3), ref) <= 1e-8
+        assert _oracle_residual_adj(orc, to_host(x3), b, kw.get("adjoint", 0)) <= 1e-10
+    # batched, with x0 aliasing x: the guess is read before x is written
+    bb = synth.gaussian_spinor(dims, 6, nrhs=3)
+    x, infos, rc = lat.solve(to_gpu(bb), tol=1e-10)
+    xs = to_host(x)
+    buf = to_gpu(xs + 1e-4 * synth.gaussian_spinor(dims, 7, nrhs=3))
+    o = wcl.wcl_default_opts()
+    o.tol = 1e-10
+    o.x0_dev = buf.data_ptr()
+    rc, infos = wcl.wcl_solve(lat.h, to_gpu(bb).data_ptr(), buf.data_ptr(), 3, o)
+    assert rc == 0
+    out = to_host(buf)
+    for k in range(3):
+        assert _oracle_residual(orc, out[k], bb[k]) <= 1e-10
+        assert rel(out[k], xs[k]) <= 1e-8
+
+
+def _oracle_residual_adj(orc, x, b, adjoint):
+    Dx = orc.D(x, dagger=bool(adjoint))
+    return float(np.linalg.norm(b - Dx) / np.linalg.norm(b))
+
+
 def test_solve_edge_cases():
     from paper_1612_06556_amd import wcl
     dims = (8, 8, 8, 8)
@@ -167,7 +255,8 @@ def test_singular_free_field_terminates():
     b = np.zeros((256, 4, 3), complex)
     b[:, 0, 0] = 1.0  # the zero mode
     x, info, rc = lat.solve(to_gpu(b), outer=wcl.OUTER_PLAIN64, max_outer=50, raise_on_error=False)
-    assert rc != 0
+    # <r~, D r> = 0 on the zero mode: every restart breaks down again
+    assert rc == wcl.WCL_EBREAKDOWN and info["status"] == wcl.WCL_EBREAKDOWN
     x, info, rc = lat.solve(to_gpu(b), max_outer=5, max_inner=20, raise_on_error=False)
     assert rc != 0
 
@@ -206,12 +295,14 @@ def test_batched_point_sources_8x4(inner_prec):
     print("batched", infos[0], flush=True)
 
 
+@pytest.mark.timeout(900)
 def test_batch12_32x64():
     """The benchmark's largest shape: 12 point sources at 32^3x64 (kappa 0.126,
     two-row links, FP16 inner with RAS) in one batched solve.  FP32 D against
     the oracle on a Gaussian field; every right-hand side's true residual
-    <= 1e-10 by the oracle's own D; x_0 within 1e-8 of a separate single
-    right-hand-side solve (the solution is unique)."""
+    <= 1e-10 by the oracle's own D; x_0 within 1e-8 of the oracle's own
+    even/odd solve of that source (converged to 1e-12) and of a separate
+    single right-hand-side solve (the solution is unique)."""
     import torch
     from paper_1612_06556_amd import wcl
     dims = (32, 32, 32, 64)
@@ -238,6 +329,10 @@ def test_batch12_32x64():
     assert rc0 == 0
     assert rel(x[0], to_host(x0)) <= 1e-8
     lat.close()
+    xr, oinfo = orc.bicgstab_eo(b[0], 1e-12, 20000)
+    err = rel(x[0], xr)
+    print(f"rhs 0 vs oracle solve ({oinfo}): {err:.3e}", flush=True)
+    assert oinfo["status"] == 0 and err <= 1e-8
 
 
 def test_batched_mixed_outer_variants():
