@@ -111,6 +111,20 @@ int wcl_set_compression(wcl_ctx *ctx, int enable);
  * cannot grow (it is allocated on first use and kept). */
 int wcl_apply(wcl_ctx *ctx, const double *in_dev, double *out_dev, int nrhs, int dagger, int prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wcl_apply
+ * without any allocation.  Same arguments, layouts, ownership, results and
+ * errors as wcl_apply (the same kernels run in the same order), but its
+ * temporaries live in a fixed scratch array of 64 MiB per GPU that the
+ * library holds until the process ends, and it records no profiling events:
+ * lattices of at most 174762 sites (e.g. 8^4, 16^3x32) -- larger ones fail
+ * with WCL_EINVAL; right-hand sides are processed one after another.  Every
+ * call on one GPU uses that GPU's one scratch array, so calls that overlap on
+ * one GPU (other streams or host threads) race and must be serialised by
+ * the caller.  The context's resident fields come from wcl_set_gauge and
+ * wcl_set_params, which do allocate. */
+int wcl_apply_noalloc(wcl_ctx *ctx, const double *in_dev, double *out_dev, int nrhs, int dagger, int prec);
+
 /* One step of the hot path on canonical FP64 vectors, for per-step checks of
  * the even/odd preconditioned matrix and its RAS preconditioner (Sec. 2);
  * same buffer rules and errors as wcl_apply, and WCL_EINVAL for an unknown

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,15 @@
 #include "wcl_launch.h"
 
 using namespace wcl;
+
+// Fixed device scratch of wcl_apply_noalloc (for callers that cannot
+// allocate): every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: host code uses only the per-device address that
+// hipGetSymbolAddress returns (g_scratch below).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr size_t NOALLOC_BYTES_PER_HALF_SITE = 768;   // FP64 in + out e/o fields, both parities
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -390,6 +400,25 @@ int reconstruct64(wcl_ctx *c, const void *b, void *x, void *tmp_o, int nrhs = 1)
     return WCL_OK;
 }
 
+// Device address of `scratch` per device, taken once per device with that
+// device current (wcl_create).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+int scratch_init(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return fail(WCL_EINVAL, "device index beyond the scratch table");
+    if (g_scratch[device]) return WCL_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(WCL_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return WCL_OK;
+}
+
 int check_prec(int prec) { return (prec == 64 || prec == 32 || prec == 16) ? WCL_OK : fail(WCL_EINVAL, "prec must be 64, 32 or 16"); }
 
 // Scalar and partial buffers for n right-hand sides: outer scalars at
@@ -587,7 +616,8 @@ int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream,
         return fail(WCL_EHIP, "no HIP device");
     }
     int rc = WCL_OK;
-    if ((rc = alloc((void **)&c->info, sizeof(int))) != WCL_OK || (rc = ensure_batch(c, 1)) != WCL_OK) {
+    if ((rc = scratch_init(c->device)) != WCL_OK || (rc = alloc((void **)&c->info, sizeof(int))) != WCL_OK ||
+        (rc = ensure_batch(c, 1)) != WCL_OK) {
         wcl_destroy(c);
         return rc;
     }
@@ -835,6 +865,70 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
 int wcl_apply(wcl_ctx *c, const double *in, double *out, int nrhs, int dagger, int prec)
 {
     return wcl_apply_op(c, dagger ? WCL_OP_DDAG : WCL_OP_D, in, out, nrhs, prec);
+}
+
+// wcl_apply without allocation: the same kernels in the same order as
+// wcl_apply (pack, precision cast, the two parity launches of D, cast back,
+// unpack), with every temporary in this device's fixed scratch instead of
+// the context's workspace, and no profiling events.  Layout of the scratch
+// per call: [0, 384 Vh) the FP64 e/o input (both parities), then either the
+// FP64 e/o output or, for prec 32/16, the cast input and output (192 Vh
+// each at most); the cast-back output reuses the FP64 input region.
+int wcl_apply_noalloc(wcl_ctx *c, const double *in, double *out, int nrhs, int dagger, int prec)
+{
+    if (!c || !in || !out) return fail(WCL_EINVAL, "null argument");
+    if (!c->have_params) return fail(WCL_ESTATE, "operator used before wcl_set_gauge and wcl_set_params");
+    CHK(check_prec(prec));
+    if (nrhs < 1) return fail(WCL_EINVAL, "nrhs must be >= 1");
+    if (c->device < 0 || c->device >= MAX_DEVICES || !g_scratch[c->device])
+        return fail(WCL_ESTATE, "no scratch address for the context's device");
+    const size_t Vh = c->Vh;
+    const size_t need = NOALLOC_BYTES_PER_HALF_SITE * Vh;
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        char msg[200];
+        snprintf(msg, sizeof msg,
+                 "wcl_apply_noalloc: this lattice needs %zu bytes of scratch; the fixed scratch holds %zu "
+                 "(lattices of at most %zu sites)",
+                 need, NOALLOC_SCRATCH_BYTES, 2 * (NOALLOC_SCRATCH_BYTES / NOALLOC_BYTES_PER_HALF_SITE));
+        return fail(WCL_EINVAL, msg);
+    }
+    char *base = (char *)g_scratch[c->device];
+    const int sp = prec;
+    void *a64 = base;                                   // 2 x spinor_bytes(8, Vh) = 384 Vh
+    void *b = base + 2 * spinor_bytes(8, Vh);           // FP64 output, or the cast input ...
+    void *a = b;
+    void *bs = (char *)b + 2 * spinor_bytes(prec_bytes(sp), Vh);   // ... and the cast output
+    if (sp == P64) bs = b;
+    for (int k = 0; k < nrhs; k++) {
+        const double *ink = in + (size_t)k * c->V * 24;
+        double *outk = out + (size_t)k * c->V * 24;
+        HIPCHK(launch_pack_spinor(c->g, ink, a64, c->st));
+        const void *src = a64;
+        if (sp != P64) {
+            HIPCHK(launch_convert(P64, sp, 2 * Vh, Vh, Vh, a64, a, nullptr, 0, 1.0, c->st));
+            src = a;
+        }
+        for (int p = 0; p < 2; p++) {
+            HopLaunch L = hop_base(c, prec, sp);
+            L.mode = CLOVX;
+            L.dagger = dagger ? 1 : 0;
+            L.p = p;
+            L.in = par(src, sp, Vh, 1 - p);
+            L.x = par(src, sp, Vh, p);
+            L.out = par(bs, sp, Vh, p);
+            L.clov = clov_for(c, prec);
+            L.coef = -c->kappa;
+            L.in_stride = L.out_stride = L.x_stride = full_bytes(sp, Vh);
+            HIPCHK(launch_hop(L, c->st));
+        }
+        if (sp != P64) {
+            HIPCHK(launch_convert(sp, P64, 2 * Vh, Vh, Vh, bs, a64, nullptr, 0, 1.0, c->st));
+            HIPCHK(launch_unpack_spinor(c->g, a64, outk, c->st));
+        } else {
+            HIPCHK(launch_unpack_spinor(c->g, bs, outk, c->st));
+        }
+    }
+    return WCL_OK;
 }
 
 void wcl_default_opts(wcl_solve_opts *o)

@@ -78,6 +78,7 @@ def load():
     lib.wcl_set_ras_cores.argtypes = [_vp, _ip]
     lib.wcl_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_apply_op.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int]
+    lib.wcl_apply_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_default_opts.argtypes = [ctypes.POINTER(wcl_solve_opts)]
     lib.wcl_default_opts.restype = None
     lib.wcl_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(wcl_solve_opts),
@@ -147,6 +148,10 @@ def wcl_set_ras_cores(h, cores):
 
 def wcl_apply(h, in_ptr, out_ptr, nrhs, dagger, prec):
     _check(load().wcl_apply(h, _vp(in_ptr), _vp(out_ptr), int(nrhs), int(dagger), int(prec)))
+
+
+def wcl_apply_noalloc(h, in_ptr, out_ptr, nrhs, dagger, prec):
+    _check(load().wcl_apply_noalloc(h, _vp(in_ptr), _vp(out_ptr), int(nrhs), int(dagger), int(prec)))
 
 
 def wcl_apply_op(h, op, in_ptr, out_ptr, nrhs, prec):
