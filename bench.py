@@ -494,7 +494,7 @@ def main():
     elapsed = time.perf_counter() - t0
     stats = {name: wcl.wcl_profile_read(lat.h, k) for name, k in classes}
     wcl.wcl_profile(lat.h, 0)
-    wcl.wcl_profile_mask(lat.h, 7)
+    wcl.wcl_profile_mask(lat.h, 15)
     ms_per_step = elapsed * 1e3 / args.steps
     total_flops = sum(s["flops"] for s in stats.values())
     value = total_flops / elapsed / 1e9

@@ -266,9 +266,12 @@ int wcl_bench_stream(wcl_ctx *ctx, double mib, int reps, double *read_gbs, doubl
  * launches; recorded around multi-kernel launches) and its
  * algorithmic HBM bytes and flops are recorded (1320 flop per hop site,
  * 504 per clover site; bytes = each link, clover site and vector once).
+ * WCL_K_INNER holds the persistent inner-solve launches (opts.persistent),
+ * timed by events around the launch, with the work of the iterations they
+ * ran (their Schur, Schwarz and vector work by the rules above).
  * wcl_profile(ctx, 1) clears and starts, (ctx, 0) stops; wcl_profile_read
  * synchronises the stream and returns the totals of one class. */
-enum { WCL_K_HOP = 0, WCL_K_RAS = 1, WCL_K_CLOVER = 2, WCL_K_COUNT = 3 };
+enum { WCL_K_HOP = 0, WCL_K_RAS = 1, WCL_K_CLOVER = 2, WCL_K_INNER = 3, WCL_K_COUNT = 4 };
 typedef struct {
     int launches;        /* launches that did work                            */
     int idle_launches;   /* launches queued after convergence (no-ops)        */

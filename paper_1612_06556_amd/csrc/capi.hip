@@ -85,6 +85,7 @@ struct wcl_ctx {
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
     int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0, hop_lds = 1;
     int hop_rhs = 1;   // right-hand sides per thread in batched launches (1, 2, 4)
+    int num_cus = 0;   // compute units of the device (one persistent workgroup each)
     // event profiling of kernel classes
     struct Rec {
         int kclass;
@@ -497,6 +498,8 @@ enum Slot {
     S_GRAS_T, S_GRAS_V, S_GRAS_S,
     // field strength planes of the clover setup
     S_CLOVF,
+    // persistent inner solve: per-workgroup partial sums, barrier counters + time-out flag
+    S_PPART, S_PBAR,
     // bench copies start here
     S_BENCH = 64,
 };
@@ -611,7 +614,8 @@ int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream,
     c->V = (int)V;
     c->Vh = g.Vh;
     c->st = (hipStream_t)hip_stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
         delete c;
         return fail(WCL_EHIP, "no HIP device");
     }
@@ -1005,6 +1009,7 @@ struct InnerCfg {
     bool graph;                    // replay the iteration as a captured hipGraph
     hipGraphExec_t *exec;          // the captured iteration (created on first use)
     hipStream_t cap_stream;        // private stream used only for the capture
+    bool persistent;               // the whole inner solve as one cooperative launch
 };
 
 // One BiCGStab iteration (right preconditioned by RAS when enabled) on the
@@ -1085,6 +1090,74 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
         HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, nullptr, c->st, n, m));
         HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st, n, SF(c)));
+    }
+    if (cfg.persistent) {
+        // every iteration in one cooperative launch, then one read of the scalars
+        void *part, *bar;
+        CHK(wsget(c, S_PPART, sizeof(double) * PMAX_WG * PMAX_RHS * 4, &part));
+        CHK(wsget(c, S_PBAR, 64, &bar));
+        PersistLaunch P{};
+        P.g = &c->g;
+        P.link_prec = eff_lprec(c, cfg.lprec);
+        P.vec_prec = vp;
+        P.links = links_for(c, P.link_prec);
+        P.clov_inv = clovinv_for(c, cfg.lprec);
+        P.kappa2 = c->kappa * c->kappa;
+        P.use_ras = cfg.ras ? 1 : 0;
+        P.overlap = c->ras_overlap;
+        P.iters = c->ras_iters;
+        P.jacobi = c->ras_solver == WCL_RAS_JACOBI;
+        P.x = w.x32; P.r = w.r32; P.rt = w.rt32; P.p = w.p32; P.v = w.v32; P.s = w.s32; P.t = w.t32;
+        P.ph = w.ph32; P.sh = w.sh32; P.o = w.o32;
+        P.stride = half_bytes(vp, Vh);
+        P.sc = sc;
+        P.partials = (double *)part;
+        P.bar = (unsigned *)bar;
+        P.err = (int *)((char *)bar + 32);
+        P.nrhs = n;
+        P.maxit = cfg.maxit;
+        P.num_cus = c->num_cus;
+        const size_t rec = c->recs.size();
+        CHK(profiled(c, WCL_K_INNER, 0.0, 0.0, [&] { return launch_persist(P, c->st); }));
+        CHK(read_sc(c, HI(c), sc, n));   // synchronises the stream
+        int err = 0;
+        HIPCHK(hipMemcpy(&err, P.err, sizeof(int), hipMemcpyDeviceToHost));
+        if (err) return fail(WCL_EHIP, "persistent inner solve: a grid barrier wait exceeded its bound");
+        for (int k = 0; k < n; k++) iters[k] = HI(c)[k].iter;
+        if (c->prof && rec < c->recs.size()) {
+            // algorithmic work of the iterations run: per iteration and
+            // right-hand side two Schur applications (two hop launches each),
+            // two Schwarz applications and the vector updates and reductions
+            double b = 0, f = 0;
+            for (int k = 0; k < n; k++) {
+                const int it = iters[k];
+                if (it <= 0) continue;
+                HopLaunch L = hop_base(c, cfg.lprec, vp);
+                L.mode = CLOV_H;
+                double hb, hf;
+                hop_work(L, &hb, &hf);
+                b += 2.0 * it * hb; f += 2.0 * it * hf;
+                L.mode = XPAY;
+                hop_work(L, &hb, &hf);
+                b += 2.0 * it * hb; f += 2.0 * it * hf;
+                if (cfg.ras) {
+                    RasLaunch R{};
+                    R.g = &c->g; R.overlap = c->ras_overlap; R.iters = c->ras_iters; R.jacobi = false;
+                    R.link_prec = P.link_prec; R.nrhs = 1; R.vec_prec = vp;
+                    double rb, rf;
+                    ras_work(R, &rb, &rf);
+                    b += 2.0 * it * rb; f += 2.0 * it * rf;
+                }
+                // p update (4 vector passes), s update (3), x / r update with dots (8), 96 flop
+                // per complex number and update or dot on 12 complex numbers per site
+                b += it * 15.0 * half_bytes(vp, Vh);
+                f += it * (double)Vh * 12.0 * (8.0 + 6.0 + 16.0 + 3 * 8.0);
+            }
+            c->recs[rec].bytes = b;
+            c->recs[rec].flops = f;
+        }
+        HIPCHK(launch_convert(vp, P64, n * Vh, Vh, Vh, w.x32, out64, &sc->t[0], 2, 1.0, c->st, 1, sstride));
+        return WCL_OK;
     }
     // Iterations are queued in chunks; every kernel of an iteration queued
     // after a right-hand side converged is a no-op for it.  The chunk length
@@ -1437,11 +1510,19 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     if (o.inner_vec_prec == 16 && o.inner_prec != 16)
         return fail(WCL_EINVAL, "FP16 inner vectors need the FP16 links and clover (inner_prec 16)");
     if (o.check_every < 1) o.check_every = 8;
-    if (o.persistent) return fail(WCL_EINVAL, "persistent inner solve not available");
+    if (o.persistent) {
+        if (o.outer != WCL_OUTER_FBICGSTAB && o.outer != WCL_OUTER_DC)
+            return fail(WCL_EINVAL, "the persistent inner solve belongs to the FBICGSTAB and DC solvers");
+        if (o.use_graph) return fail(WCL_EINVAL, "persistent and use_graph are exclusive");
+        if (nrhs > PMAX_RHS) return fail(WCL_EINVAL, "the persistent inner solve takes at most 16 right-hand sides");
+    }
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
     const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
     const bool inner = !plain && !plain_eo;
     if (o.use_ras && inner) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver, o.ras_mult));
+    if (o.persistent && o.use_ras && (ras_generic(c) || c->ras_mult || c->ras_solver != WCL_RAS_MR))
+        return fail(WCL_EINVAL, "the persistent inner solve runs the additive Schwarz with minimal-residual "
+                                "blocks of the fused kernel (tile cores, at most 648 sites per parity)");
     const int n = nrhs;
     CHK(ensure_batch(c, n));
     SolveWs w;
@@ -1459,7 +1540,7 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
         }
     } guard{&graph_exec, &cap_stream};
     InnerCfg cfg{o.inner_prec, o.inner_vec_prec, o.inner_tol, o.max_inner, o.use_ras != 0, o.check_every,
-                 o.use_graph != 0 && inner, &graph_exec, cap_stream};
+                 o.use_graph != 0 && inner, &graph_exec, cap_stream, o.persistent != 0 && inner};
     // the inner stopping threshold is fixed for the whole solve
     for (int k = 0; k < n; k++) {
         HI(c)[k] = Scalars{};

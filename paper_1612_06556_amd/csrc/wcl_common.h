@@ -674,6 +674,17 @@ WCL_D void su3_dag_mul(const cplx<R> u[9], const cplx<R> h[6], cplx<R> o[6])
         }
 }
 
+// The thread's index in its workgroup as a value the compiler cannot prove
+// loop-invariant: per-thread arithmetic of a code path that runs inside a
+// long kernel loop (the persistent solver's phases) stays in that path
+// instead of being hoisted to the kernel entry and held in registers.
+WCL_D unsigned tid_here()
+{
+    unsigned t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // XCD-aware workgroup order: consecutive logical tiles land on one XCD
 // (workgroups are dealt round-robin over the 8 XCDs).
 WCL_D int xcd_block(int bid, int nblk)

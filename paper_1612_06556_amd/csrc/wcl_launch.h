@@ -185,6 +185,32 @@ struct RasLaunch {
 };
 hipError_t launch_ras(const RasLaunch &a, hipStream_t st);
 
+// The inner single-precision BiCGStab (right preconditioned by the fused
+// additive RAS, minimal-residual blocks, or unpreconditioned) as one
+// persistent cooperative launch: every iteration until each right-hand side
+// has converged (scalars sc, initialised as after BICG_INIT_RHO with stop2
+// set) or maxit iterations have run.  One workgroup per CU; partials holds
+// PMAX_WG x PMAX_RHS x 4 doubles; bar (2 unsigned) and err (1 int) are the
+// grid barrier's counters and time-out flag (reset by the launch).
+constexpr int PMAX_WG = 1024;
+constexpr int PMAX_RHS = 16;
+struct PersistLaunch {
+    const Geom *g;
+    int link_prec, vec_prec;
+    const void *links, *clov_inv;
+    double kappa2;
+    int use_ras, overlap, iters;
+    bool jacobi;
+    void *x, *r, *rt, *p, *v, *s, *t, *ph, *sh, *o;   // [nrhs] even fields, stride bytes apart
+    size_t stride;
+    Scalars *sc;
+    double *partials;
+    unsigned *bar;
+    int *err;
+    int nrhs, maxit, num_cus;
+};
+hipError_t launch_persist(const PersistLaunch &L, hipStream_t st);
+
 // Schwarz block solves with the block vectors in global memory (any core
 // size and overlap that fit the lattice; block solver 0 minimal residual,
 // 1 Jacobi, 2 BiCGStab).  A plan holds the geometry tables and the block

@@ -54,7 +54,7 @@ class wcl_kstat(ctypes.Structure):
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double), ("idle_ms", ctypes.c_double)]
 
 
-K_HOP, K_RAS, K_CLOVER = 0, 1, 2
+K_HOP, K_RAS, K_CLOVER, K_INNER = 0, 1, 2, 3
 
 _lib = None
 _ip = ctypes.POINTER(ctypes.c_int)

@@ -197,9 +197,9 @@ def test_profile_mask_times_selected_classes():
         assert hop["launches"] > 0 and hop["flops"] > 0 and ras["launches"] > 0
         assert ras["ms"] > 0
         assert (hop["ms"] > 0) == hop_timed
-    wcl.wcl_profile_mask(lat.h, 7)
+    wcl.wcl_profile_mask(lat.h, 15)
     with pytest.raises(wcl.WclError):
-        wcl.wcl_profile_mask(lat.h, 8)
+        wcl.wcl_profile_mask(lat.h, 16)
 
 
 def test_bench_entry_points():
