@@ -306,6 +306,44 @@ int wcl_autotune_hop(wcl_ctx *ctx, int prec, int copies, int *best);
  * Applies to depth-2, non-dagger launches (temporal or non-temporal operator
  * loads); results are bitwise those of the unstaged kernel.  enable = 0 switches it off. */
 int wcl_set_hop_staging(wcl_ctx *ctx, int enable);
+/* Not in the paper (tuning).  The project autotuner: picks, by measurement,
+ *   (flags & WCL_TUNE_HOP)    the hopping kernel's launch shape -- threads per
+ *                             workgroup 64/128/256, pipeline depth 2/3, XCD
+ *                             order 0/1, site blocks per workgroup 1/2 -- timed
+ *                             with wcl_bench_hop at `prec` on nrhs right-hand
+ *                             sides (4 field copies);
+ *   (flags & WCL_TUNE_BATCH)  right-hand sides per thread 1/2/4 of the batched
+ *                             launches (nrhs > 1);
+ *   (flags & WCL_TUNE_SCHWARZ) the Schwarz choice of the solve opts describes
+ *                             -- its own overlap, overlap 0, or no Schwarz --
+ *                             by the measured time of wcl_solve(b_dev, opts)
+ *                             (b_dev: nrhs canonical sources; needs opts);
+ * every candidate being a shape the library's parity tests cover.  The
+ * chosen launch shapes are set in the context; the Schwarz choice is
+ * returned in *out (use_ras, ras_overlap) for the caller's opts.  Results
+ * are cached per process, keyed by lattice, boundary condition, tiles,
+ * precision, link storage, nrhs and flags (out->cached = 1 on a hit, the
+ * shapes are then set without timing).  WCL_EINVAL for bad arguments. */
+enum { WCL_TUNE_HOP = 1, WCL_TUNE_BATCH = 2, WCL_TUNE_SCHWARZ = 4 };
+typedef struct {
+    int hop_block;        /* hopping launch shape: threads per workgroup        */
+    int hop_depth;        /*   pipeline depth                                   */
+    int hop_xcd;          /*   XCD-aware workgroup order                        */
+    int hop_tiles;        /*   site blocks per workgroup                        */
+    int rhs_per_thread;   /* batched launches                                   */
+    int use_ras;          /* Schwarz choice: on / off                           */
+    int ras_overlap;      /*   extension of the cores                          */
+    int cached;           /* 1: the result came from the cache                  */
+    double hop_ms;        /* launch time of the chosen hop shape (ms)          */
+    double solve_ms;      /* time of the solve with the chosen Schwarz (ms)    */
+} wcl_tuning;
+int wcl_autotune(wcl_ctx *ctx, int prec, int nrhs, const double *b_dev, const wcl_solve_opts *opts, int flags,
+                 wcl_tuning *out);
+/* Consecutive site blocks (of the workgroup size) each hop workgroup takes
+ * in turn (1, 2, 4 or 8; default 1): fewer, longer-lived workgroups, each
+ * sweeping one contiguous range of every field.  Results are bitwise those
+ * of one block per workgroup.  WCL_EINVAL for other values. */
+int wcl_set_hop_tiles(wcl_ctx *ctx, int tiles);
 /* Batched launches (nrhs > 1) of the FP32-vector hopping kernels (the inner
  * solver's Schur halves): rhs_per_thread = 1 gives each right-hand side its
  * own workgroups (links shared through L2); 2 or 4 keep that many right-hand

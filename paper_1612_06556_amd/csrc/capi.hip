@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -78,13 +79,15 @@ struct wcl_ctx {
     GrasPlan gras{};                   // block fields of the global-memory Schwarz path
     bool gras_ready = false;
     std::vector<Buf> ws;        // workspace, indexed by slot
-    double *partials = nullptr; // [cap][6][RED_BLOCKS]
+    double *partials = nullptr; // [cap][6][pstride]
+    int pstride = 0;            // partial sums per term and right-hand side (>= every launch's workgroups)
     Scalars *sc = nullptr;      // [3][cap]: outer, inner, final/scratch scalars per right-hand side
     Scalars *sc_host = nullptr; // pinned mirror
     int cap = 0;                // right-hand sides the scalar and partial buffers hold
     // hopping-kernel launch configuration (set by wcl_set_tuning / wcl_autotune_hop)
     int hop_block = 256, hop_depth = 2, hop_xcd = 1, hop_nt = 0, hop_lds = 1;
     int hop_rhs = 1;   // right-hand sides per thread in batched launches (1, 2, 4)
+    int hop_tpw = 1;   // consecutive site blocks per hop workgroup
     int num_cus = 0;   // compute units of the device (one persistent workgroup each)
     // event profiling of kernel classes
     struct Rec {
@@ -175,6 +178,7 @@ HopLaunch hop_base(wcl_ctx *c, int lprec, int sprec)
     L.block = c->hop_block;
     L.depth = c->hop_depth;
     L.rhs_per_thread = c->hop_rhs;
+    L.tpw = c->hop_tpw;
     L.nontemporal = c->hop_nt;
     L.lds_stage = c->hop_lds;
     return L;
@@ -361,6 +365,37 @@ int schur(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void 
     return WCL_OK;
 }
 
+// Schur operator with the BiCGStab reductions fused into its second half:
+// ndot 1: partials of <w, out>; ndot 2: of <out, w> and <out, out>, at
+// c->partials (stride c->pstride), *nparts per term.
+int schur_dot(wcl_ctx *c, int lprec, int sprec, const void *in_e, void *out_e, void *tmp_o, const Scalars *sc,
+              int nrhs, int ndot, const void *w, int *nparts)
+{
+    HopLaunch L = hop_base(c, lprec, sprec);
+    L.clov = clovinv_for(c, lprec);
+    L.sc = sc;
+    L.nrhs = nrhs;
+    L.in_stride = L.out_stride = L.x_stride = half_bytes(sprec, c->Vh);
+    L.mode = CLOV_H;
+    L.p = 1;
+    L.in = in_e;
+    L.out = tmp_o;
+    CHK(run_hop(c, L));
+    L.mode = XPAY;
+    L.p = 0;
+    L.in = tmp_o;
+    L.x = in_e;
+    L.out = out_e;
+    L.coef = -c->kappa * c->kappa;
+    L.ndot = ndot;
+    L.dotw = w;
+    L.partials = c->partials;
+    L.pstride = c->pstride;
+    *nparts = hop_parts(L);
+    CHK(run_hop(c, L));
+    return WCL_OK;
+}
+
 // bhat_e = A_ee^-1 (b_e + k H_eo A_oo^-1 b_o)  (b: full FP64 fields, bhat, tmp: even/odd FP64 vectors)
 int schur_rhs64(wcl_ctx *c, const void *b, void *bhat_e, void *tmp_o, void *tmp_e, int nrhs = 1)
 {
@@ -433,7 +468,7 @@ int ensure_batch(wcl_ctx *c, int n)
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     c->sc = nullptr; c->partials = nullptr; c->sc_host = nullptr; c->cap = 0;
     CHK(alloc((void **)&c->sc, sizeof(Scalars) * 3 * n));
-    CHK(alloc((void **)&c->partials, sizeof(double) * 6 * RED_BLOCKS * n));
+    CHK(alloc((void **)&c->partials, sizeof(double) * 6 * (size_t)c->pstride * n));
     if (hipHostMalloc((void **)&c->sc_host, sizeof(Scalars) * 3 * n, hipHostMallocDefault) != hipSuccess)
         return fail(WCL_ENOMEM, "hipHostMalloc failed");
     memset(c->sc_host, 0, sizeof(Scalars) * 3 * n);
@@ -466,8 +501,8 @@ int write_sc(wcl_ctx *c, Scalars *dev, const Scalars *host, int n)
 int norms_dev(wcl_ctx *c, int prec, size_t m, const void *v, size_t stride, int n, Scalars *dst)
 {
     const void *a[1] = {v}, *b[1] = {v};
-    HIPCHK(launch_dots(prec, m, 1, a, b, c->partials, nullptr, c->st, n, stride));
-    HIPCHK(launch_finalize(NORM_ONLY, 2, c->partials, dst, c->st, n));
+    HIPCHK(launch_dots(prec, m, 1, a, b, c->partials, nullptr, c->st, n, stride, c->pstride));
+    HIPCHK(launch_finalize(NORM_ONLY, 2, c->partials, dst, c->st, n, nullptr, c->pstride));
     return WCL_OK;
 }
 
@@ -613,6 +648,9 @@ int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream,
     g.dB2 = make_fastdiv(B[2]);
     c->V = (int)V;
     c->Vh = g.Vh;
+    // partial sums per term: the BLAS grids (<= 8192 workgroups) and the hop
+    // launches with fused reductions (one workgroup per 64 or more sites)
+    c->pstride = std::max(8192, (g.Vh + 63) / 64);
     c->st = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
@@ -1040,11 +1078,18 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         else CHK(run_ras(c, R));
         ph = w.ph32;
     }
-    CHK(schur(c, lp, vp, ph, w.v32, w.o32, sc, n));
-    {
+    // the reductions ride in the Schur operator's second half and the x, r
+    // update, except with several right-hand sides per thread
+    const bool fused = c->hop_rhs == 1 || n == 1;
+    int np = 0;
+    if (fused) {
+        CHK(schur_dot(c, lp, vp, ph, w.v32, w.o32, sc, n, 1, w.rt32, &np));
+        HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+    } else {
+        CHK(schur(c, lp, vp, ph, w.v32, w.o32, sc, n));
         const void *a[1] = {w.rt32}, *b[1] = {w.v32};
-        HIPCHK(launch_dots(vp, m, 1, a, b, c->partials, sc, c->st, n, m));
-        HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n));
+        HIPCHK(launch_dots(vp, m, 1, a, b, c->partials, sc, c->st, n, m, c->pstride));
+        HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n, nullptr, c->pstride));
     }
     HIPCHK(launch_bicg_s(vp, m, w.r32, w.v32, w.s32, sc, c->st, n, m));
     if (cfg.ras) {
@@ -1054,17 +1099,25 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         else CHK(run_ras(c, R));
         sh = w.sh32;
     }
-    CHK(schur(c, lp, vp, sh, w.t32, w.o32, sc, n));
-    {
-        const void *a[2] = {w.t32, w.t32}, *b[2] = {w.s32, w.t32};
-        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m));
-        HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n));
-    }
-    HIPCHK(launch_bicg_xr(vp, m, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st, n, m));
-    {
-        const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m));
-        HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n));
+    if (fused) {
+        CHK(schur_dot(c, lp, vp, sh, w.t32, w.o32, sc, n, 2, w.s32, &np));
+        HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+        HIPCHK(launch_bicg_xr_dots(vp, m, w.x32, ph, sh, w.r32, w.s32, w.t32, w.rt32, sc, c->st, n, m, c->partials,
+                                   c->pstride, &np));
+        HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+    } else {
+        CHK(schur(c, lp, vp, sh, w.t32, w.o32, sc, n));
+        {
+            const void *a[2] = {w.t32, w.t32}, *b[2] = {w.s32, w.t32};
+            HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+            HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
+        }
+        HIPCHK(launch_bicg_xr(vp, m, w.x32, ph, sh, w.r32, w.s32, w.t32, sc, c->st, n, m));
+        {
+            const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
+            HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+            HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
+        }
     }
     return WCL_OK;
 }
@@ -1088,8 +1141,8 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
     HIPCHK(launch_zero(vp, n * m, w.v32, c->st));
     {
         const void *a[2] = {w.rt32, w.r32}, *b[2] = {w.r32, w.r32};
-        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, nullptr, c->st, n, m));
-        HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st, n, SF(c)));
+        HIPCHK(launch_dots(vp, m, 2, a, b, c->partials, nullptr, c->st, n, m, c->pstride));
+        HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, sc, c->st, n, SF(c), c->pstride));
     }
     if (cfg.persistent) {
         // every iteration in one cooperative launch, then one read of the scalars
@@ -1296,8 +1349,8 @@ int restart(wcl_ctx *c, const Driver &d, SolveWs &w, int k, double tol, const st
     HIPCHK(launch_zero(P64, cnt * d.m, (char *)w.p + off, c->st));
     HIPCHK(launch_zero(P64, cnt * d.m, (char *)w.v + off, c->st));
     const void *a[2] = {(char *)w.rt + off, (char *)w.r + off}, *b[2] = {(char *)w.r + off, (char *)w.r + off};
-    HIPCHK(launch_dots(P64, d.m, 2, a, b, c->partials, nullptr, c->st, cnt, d.m));
-    HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, SO(c) + k0, c->st, cnt, SF(c) + k0));
+    HIPCHK(launch_dots(P64, d.m, 2, a, b, c->partials, nullptr, c->st, cnt, d.m, c->pstride));
+    HIPCHK(launch_finalize(BICG_INIT_RHO, 4, c->partials, SO(c) + k0, c->st, cnt, SF(c) + k0, c->pstride));
     CHK(read_sc(c, HO(c) + k0, SO(c) + k0, cnt));
     for (int j = k0; j < k0 + cnt; j++) {
         Scalars &h = HO(c)[j];
@@ -1375,8 +1428,8 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
             CHK(apply_A(c, d, w, ph, w.v, sc));
             {
                 const void *a[1] = {w.rt}, *b[1] = {w.v};
-                HIPCHK(launch_dots(P64, m, 1, a, b, c->partials, sc, c->st, n, m));
-                HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n));
+                HIPCHK(launch_dots(P64, m, 1, a, b, c->partials, sc, c->st, n, m, c->pstride));
+                HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n, nullptr, c->pstride));
             }
             HIPCHK(launch_bicg_s(P64, m, w.r, w.v, w.s, sc, c->st, n, m));
             if (d.flex) {
@@ -1387,14 +1440,14 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
             CHK(apply_A(c, d, w, sh, w.t, sc));
             {
                 const void *a[2] = {w.t, w.t}, *b[2] = {w.s, w.t};
-                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m));
-                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n));
+                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
             }
             HIPCHK(launch_bicg_xr(P64, m, d.x, ph, sh, w.r, w.s, w.t, sc, c->st, n, m));
             {
                 const void *a[2] = {w.rt, w.r}, *b[2] = {w.r, w.r};
-                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m));
-                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n));
+                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
             }
         }
         iter += chunk;
@@ -1721,7 +1774,7 @@ extern "C" int wcl_bench_stream(wcl_ctx *c, double mib, int reps, double *read_g
     if (!c || !read_gbs || !copy_gbs) return fail(WCL_EINVAL, "null argument");
     if (!(mib >= 1.0 && mib <= 65536.0) || reps < 1) return fail(WCL_EINVAL, "1 <= mib <= 65536 and reps >= 1 required");
     const size_t bytes = ((size_t)(mib * 1048576.0) / 16) * 16, n16 = bytes / 16;
-    const int blocks = 8192;
+    const int blocks = 4 * std::max(c->num_cus, 1);
     void *a, *b, *out;
     CHK(wsget(c, S_BENCH, bytes, &a));
     CHK(wsget(c, S_BENCH + 1, bytes, &b));
@@ -1767,14 +1820,16 @@ extern "C" int wcl_grad(wcl_ctx *c, const double *x, const double *y, double *gU
     }
     HIPCHK(launch_sigmaF(c->g, c->U64, X, CX, c->st));
     const void *a[2] = {Y, Y}, *b[2] = {HX, CX};
-    HIPCHK(launch_dots(P64, 24 * Vh, 2, a, b, c->partials, nullptr, c->st));
-    double part[4 * RED_BLOCKS];
-    HIPCHK(hipMemcpyAsync(part, c->partials, sizeof(part), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(launch_dots(P64, 24 * Vh, 2, a, b, c->partials, nullptr, c->st, 1, 0, c->pstride));
+    double part[2][RED_BLOCKS];   // the real parts of <y, Hx> and <y, Cx> (terms 0 and 2)
+    HIPCHK(hipMemcpyAsync(part[0], c->partials, sizeof(part[0]), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(part[1], c->partials + 2 * (size_t)c->pstride, sizeof(part[1]), hipMemcpyDeviceToHost,
+                          c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     double yhx = 0.0, ycx = 0.0;
     for (int j = 0; j < RED_BLOCKS; j++) {
-        yhx += part[0 * RED_BLOCKS + j];
-        ycx += part[2 * RED_BLOCKS + j];
+        yhx += part[0][j];
+        ycx += part[1][j];
     }
     *gk = yhx + c->csw * ycx;
     return WCL_OK;
@@ -1840,6 +1895,14 @@ extern "C" int wcl_set_tuning(wcl_ctx *c, int hop_block, int hop_depth, int hop_
     return WCL_OK;
 }
 
+extern "C" int wcl_set_hop_tiles(wcl_ctx *c, int tiles)
+{
+    if (!c) return fail(WCL_EINVAL, "null context");
+    if (tiles != 1 && tiles != 2 && tiles != 4 && tiles != 8) return fail(WCL_EINVAL, "tiles must be 1, 2, 4 or 8");
+    c->hop_tpw = tiles;
+    return WCL_OK;
+}
+
 extern "C" int wcl_set_hop_staging(wcl_ctx *c, int enable)
 {
     if (!c) return fail(WCL_EINVAL, "null context");
@@ -1853,6 +1916,121 @@ extern "C" int wcl_set_batch_tuning(wcl_ctx *c, int rhs_per_thread)
     if (rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4)
         return fail(WCL_EINVAL, "rhs_per_thread must be 1, 2 or 4");
     c->hop_rhs = rhs_per_thread;
+    return WCL_OK;
+}
+
+namespace {
+struct TuneKey {
+    int L[4], B[4], tbc, prec, compress, nrhs, flags, device;
+    bool operator<(const TuneKey &o) const { return memcmp(this, &o, sizeof(TuneKey)) < 0; }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, wcl_tuning> g_tune_cache;
+}  // namespace
+
+extern "C" int wcl_autotune(wcl_ctx *c, int prec, int nrhs, const double *b, const wcl_solve_opts *opts, int flags,
+                            wcl_tuning *out)
+{
+    if (!c || !out) return fail(WCL_EINVAL, "null argument");
+    if (prec != 32 && prec != 16) return fail(WCL_EINVAL, "autotune prec must be 32 or 16");
+    if (nrhs < 1 || nrhs > 64) return fail(WCL_EINVAL, "autotune nrhs must be 1 .. 64");
+    if (flags <= 0 || flags > (WCL_TUNE_HOP | WCL_TUNE_BATCH | WCL_TUNE_SCHWARZ))
+        return fail(WCL_EINVAL, "unknown autotune flags");
+    if ((flags & WCL_TUNE_SCHWARZ) && (!b || !opts)) return fail(WCL_EINVAL, "Schwarz tuning needs b_dev and opts");
+    TuneKey key;
+    memset(&key, 0, sizeof(key));
+    for (int mu = 0; mu < 4; mu++) { key.L[mu] = c->g.L[mu]; key.B[mu] = c->g.B[mu]; }
+    key.tbc = c->g.tbc; key.prec = prec; key.compress = c->compress; key.nrhs = nrhs; key.flags = flags;
+    key.device = c->device;
+    wcl_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.hop_block = c->hop_block; t.hop_depth = c->hop_depth; t.hop_xcd = c->hop_xcd; t.hop_tiles = c->hop_tpw;
+    t.rhs_per_thread = c->hop_rhs;
+    t.use_ras = opts ? opts->use_ras : 1;
+    t.ras_overlap = opts ? opts->ras_overlap : c->ras_overlap;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            t = it->second;
+            t.cached = 1;
+        }
+    }
+    if (t.cached) {
+        CHK(wcl_set_tuning(c, t.hop_block, t.hop_depth, t.hop_xcd, c->hop_nt));
+        CHK(wcl_set_hop_tiles(c, t.hop_tiles));
+        CHK(wcl_set_batch_tuning(c, t.rhs_per_thread));
+        *out = t;
+        return WCL_OK;
+    }
+    if (flags & WCL_TUNE_HOP) {
+        const int blocks[3] = {64, 128, 256}, depths[2] = {2, 3}, tiles[2] = {1, 2};
+        double best = 1e30;
+        for (int xcd = 0; xcd < 2; xcd++)
+            for (int ib = 0; ib < 3; ib++)
+                for (int io = 0; io < 2; io++)
+                    for (int it = 0; it < 2; it++) {
+                        CHK(wcl_set_tuning(c, blocks[ib], depths[io], xcd, c->hop_nt));
+                        CHK(wcl_set_hop_tiles(c, tiles[it]));
+                        double ms;
+                        CHK(wcl_bench_hop(c, prec, nrhs, 20, 4, &ms));
+                        if (ms < best) {
+                            best = ms;
+                            t.hop_block = blocks[ib]; t.hop_depth = depths[io]; t.hop_xcd = xcd; t.hop_tiles = tiles[it];
+                        }
+                    }
+        CHK(wcl_set_tuning(c, t.hop_block, t.hop_depth, t.hop_xcd, c->hop_nt));
+        CHK(wcl_set_hop_tiles(c, t.hop_tiles));
+        t.hop_ms = best;
+    }
+    if ((flags & WCL_TUNE_BATCH) && nrhs > 1) {
+        const int rpt[3] = {1, 2, 4};
+        double best = 1e30;
+        for (int k = 0; k < 3; k++) {
+            CHK(wcl_set_batch_tuning(c, rpt[k]));
+            double ms;
+            CHK(wcl_bench_hop(c, prec, nrhs, 20, 4, &ms));
+            if (ms < best) { best = ms; t.rhs_per_thread = rpt[k]; }
+        }
+        CHK(wcl_set_batch_tuning(c, t.rhs_per_thread));
+        if (!(flags & WCL_TUNE_HOP)) t.hop_ms = best;
+    }
+    if (flags & WCL_TUNE_SCHWARZ) {
+        // candidates: the given recipe, the same without overlap, no Schwarz;
+        // each solve once untimed (workspace, clover caches), then timed
+        const size_t bytes = (size_t)nrhs * c->V * 24 * sizeof(double);
+        void *x = nullptr;
+        CHK(alloc(&x, bytes));
+        struct Free { void *p; ~Free() { if (p) (void)hipFree(p); } } guard{x};
+        std::vector<wcl_solve_info> info(nrhs);
+        const int cand_ras[3] = {1, 1, 0}, cand_ov[3] = {opts->ras_overlap, 0, opts->ras_overlap};
+        double best = 1e30;
+        for (int k = 0; k < 3; k++) {
+            if (k == 1 && opts->ras_overlap == 0) continue;
+            wcl_solve_opts o = *opts;
+            o.use_ras = cand_ras[k];
+            o.ras_overlap = cand_ov[k];
+            o.x0_dev = nullptr;
+            const int rc0 = wcl_solve(c, b, (double *)x, nrhs, &o, info.data());
+            if (rc0 != WCL_OK) continue;   // a recipe that does not converge is not a candidate
+            HIPCHK(hipStreamSynchronize(c->st));
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = wcl_solve(c, b, (double *)x, nrhs, &o, info.data());
+            HIPCHK(hipStreamSynchronize(c->st));
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rc == WCL_OK && ms < best) { best = ms; t.use_ras = o.use_ras; t.ras_overlap = o.ras_overlap; }
+        }
+        if (best == 1e30) return fail(WCL_ENOCONV, "autotune: no Schwarz candidate solved the system");
+        t.solve_ms = best;
+        // leave the context's Schwarz settings as the caller's opts had them
+        if (opts->use_ras) CHK(wcl_set_ras(c, opts->ras_overlap, opts->ras_iters, opts->ras_solver, opts->ras_mult));
+    }
+    t.cached = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = t;
+    }
+    *out = t;
     return WCL_OK;
 }
 

@@ -24,6 +24,7 @@ struct HopArgs {
     int xcd;
     int nrhs;
     const Scalars *sc;   // per right-hand side
+    int tpw;             // consecutive site blocks per workgroup (k_hop)
 };
 
 // The 8 hops of a site run as a two-stage pipeline: the neighbour spinor and
@@ -240,5 +241,10 @@ WCL_D void hop_block(const HopArgs &a, int bid, int rhs, uint4 *sin, const void 
         }
     }
 }
+
+struct HopLaunch;
+// The XPAY hop with fused reductions (HopLaunch::ndot), grid and block as for
+// k_hop with one right-hand side per workgroup.
+hipError_t launch_hop_dot(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 block, hipStream_t st);
 
 }  // namespace wcl

@@ -485,13 +485,21 @@ __global__ void __launch_bounds__(256) k_hop(HopArgs a)
     // workgroup id = site block * nrhs + rhs: the nrhs workgroups of one site
     // block are neighbours in dispatch order (and on one XCD), so each link
     // is fetched from HBM once and served to the other right-hand sides by L2
+    // A workgroup takes tpw consecutive site blocks (one contiguous range of
+    // every field), one after another.
     const int lin = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int rhs = lin % a.nrhs;
-    const int bid = lin / a.nrhs;
+    const int grp = lin / a.nrhs;
     if (a.sc && a.sc[rhs].done) return;
     constexpr int NWORDS = (int)sizeof(SS) * 24 / 16;
     __shared__ uint4 sin[NS > 0 ? NWORDS * NS : 1];
-    hop_block<SL, SS, MODE, DAG, DEPTH, NT, NS>(a, bid, rhs, sin);
+    const int nb = (a.g.Vh + blockDim.x - 1) / blockDim.x;
+    for (int k = 0; k < a.tpw; k++) {
+        const int bid = grp * a.tpw + k;
+        if (bid >= nb) break;                 // uniform in the workgroup
+        if (NS > 0 && k) __syncthreads();     // the previous block's staged input is read
+        hop_block<SL, SS, MODE, DAG, DEPTH, NT, NS>(a, bid, rhs, sin);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -670,6 +678,12 @@ static void hop_dispatch_mode(const HopLaunch &L, const HopArgs &a, dim3 grid, d
     }
 }
 
+int hop_parts(const HopLaunch &L)
+{
+    const int bs = L.block > 0 ? L.block : 256;
+    return (L.g->Vh + bs - 1) / bs;
+}
+
 hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
 {
     if (L.nrhs < 1 || L.nrhs > 4096) return hipErrorInvalidValue;
@@ -692,10 +706,18 @@ hipError_t launch_hop(const HopLaunch &L, hipStream_t st)
     a.xcd = L.xcd;
     a.sc = L.sc;
     a.nrhs = L.nrhs;
+    a.tpw = 1;
     const int bs = L.block > 0 ? L.block : 256;
     if (bs > 256 || bs % 64) return hipErrorInvalidValue;
-    dim3 grid(((a.g.Vh + bs - 1) / bs) * a.nrhs);
+    const int nb = (a.g.Vh + bs - 1) / bs;
+    dim3 grid(nb * a.nrhs);
     dim3 block(bs);
+    if (L.ndot) return launch_hop_dot(L, a, grid, block, st);
+    if (L.tpw > 1) {
+        if (L.tpw > 64) return hipErrorInvalidValue;
+        a.tpw = L.tpw;
+        grid = dim3(((nb + L.tpw - 1) / L.tpw) * a.nrhs);
+    }
     if ((L.rhs_per_thread == 2 || L.rhs_per_thread == 4) && a.nrhs >= 2 && L.spin_prec == P32 && !L.dagger &&
         L.mode != CLOVX) {
         switch (L.link_prec) {
@@ -846,7 +868,8 @@ template <typename T, int NP>
 __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, size_t stride, const typename CT<T>::V *a0,
                                                       const typename CT<T>::V *b0, const typename CT<T>::V *a1,
                                                       const typename CT<T>::V *b1, const typename CT<T>::V *a2,
-                                                      const typename CT<T>::V *b2, double *partials, const Scalars *sc)
+                                                      const typename CT<T>::V *b2, double *partials, const Scalars *sc,
+                                                      int pstride)
 {
     const int rhs = blockIdx.y;
     if (sc && sc[rhs].done) return;
@@ -866,22 +889,23 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, size_t stride, c
     }
     block_sum<2 * NP>(v, lds);
     if (threadIdx.x == 0) {
-        double *pr = partials + (size_t)rhs * 6 * RED_BLOCKS;
+        double *pr = partials + (size_t)rhs * 6 * pstride;
 #pragma unroll
-        for (int k = 0; k < 2 * NP; k++) pr[k * RED_BLOCKS + blockIdx.x] = v[k];
+        for (int k = 0; k < 2 * NP; k++) pr[k * pstride + blockIdx.x] = v[k];
     }
 }
 
 hipError_t launch_dots(int prec, size_t n, int np, const void *const *a, const void *const *b, double *partials,
-                       const Scalars *sc, hipStream_t st, int nrhs, size_t stride)
+                       const Scalars *sc, hipStream_t st, int nrhs, size_t stride, int pstride)
 {
+    if (pstride < RED_BLOCKS) return hipErrorInvalidValue;
     const void *A[3] = {a[0], np > 1 ? a[1] : a[0], np > 2 ? a[2] : a[0]};
     const void *B[3] = {b[0], np > 1 ? b[1] : b[0], np > 2 ? b[2] : b[0]};
     dim3 grid(RED_BLOCKS, nrhs), block(RED_THREADS);
 #define WCL_DOTS(T, NP)                                                                                   \
     k_dots<T, NP><<<grid, block, 0, st>>>(n, stride, (const CT<T>::V *)A[0], (const CT<T>::V *)B[0],      \
                                           (const CT<T>::V *)A[1], (const CT<T>::V *)B[1],                 \
-                                          (const CT<T>::V *)A[2], (const CT<T>::V *)B[2], partials, sc)
+                                          (const CT<T>::V *)A[2], (const CT<T>::V *)B[2], partials, sc, pstride)
     if (prec == P64) {
         if (np == 1) WCL_DOTS(double, 1);
         else if (np == 2) WCL_DOTS(double, 2);
@@ -910,12 +934,12 @@ WCL_D void cdiv(const double a[2], const double b[2], double o[2])
 
 // One workgroup per right-hand side.  gate (optional): a right-hand side
 // whose gate scalars are done is marked done at BICG_INIT_RHO.
-__global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const double *partials_all, Scalars *sc_all,
-                                                  const Scalars *gate)
+__global__ void __launch_bounds__(512) k_finalize(int step, int nterms, const double *partials_all, Scalars *sc_all,
+                                                  const Scalars *gate, int pstride, int nparts)
 {
     const int rhs = blockIdx.x;
     Scalars *sc = sc_all + rhs;
-    const double *partials = partials_all + (size_t)rhs * 6 * RED_BLOCKS;
+    const double *partials = partials_all + (size_t)rhs * 6 * pstride;
     if (sc->done && (step == BICG_ALPHA || step == BICG_OMEGA || step == BICG_RHO)) return;
     __shared__ double lds[6 * 16];
     double v[6];
@@ -923,7 +947,7 @@ __global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const do
     for (int k = 0; k < 6; k++) {
         double t = 0.0;
         if (k < nterms)
-            for (int j = threadIdx.x; j < RED_BLOCKS; j += blockDim.x) t += partials[k * RED_BLOCKS + j];
+            for (int j = threadIdx.x; j < nparts; j += blockDim.x) t += partials[k * pstride + j];
         v[k] = t;
     }
     block_sum<6>(v, lds);
@@ -972,9 +996,10 @@ __global__ void __launch_bounds__(256) k_finalize(int step, int nterms, const do
 }
 
 hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st, int nrhs,
-                           const Scalars *gate)
+                           const Scalars *gate, int pstride, int nparts)
 {
-    k_finalize<<<nrhs, 256, 0, st>>>(step, nterms, partials, sc, gate);
+    if (nparts < 1 || nparts > pstride) return hipErrorInvalidValue;
+    k_finalize<<<nrhs, 512, 0, st>>>(step, nterms, partials, sc, gate, pstride, nparts);
     return hipGetLastError();
 }
 
@@ -1041,6 +1066,42 @@ __global__ void __launch_bounds__(256) k_bicg_xr(size_t n, size_t stride, typena
     }
 }
 
+// x += alpha ph + omega sh; r = s - omega t, with the partials of <rt, r>
+// and <r, r> (of the stored r) per workgroup: terms 0, 1 = Re, Im <rt, r>,
+// 2 = <r, r>, 3 = 0 at partials[rhs][k][block] (stride pstride).
+template <typename T>
+__global__ void __launch_bounds__(256) k_bicg_xr_dots(size_t n, size_t stride, typename CT<T>::V *x,
+                                                     const typename CT<T>::V *ph, const typename CT<T>::V *sh,
+                                                     typename CT<T>::V *r, const typename CT<T>::V *s,
+                                                     const typename CT<T>::V *t, const typename CT<T>::V *rt,
+                                                     const Scalars *sc_all, double *partials, int pstride)
+{
+    const Scalars *sc = sc_all + blockIdx.y;
+    if (sc->done) return;
+    __shared__ double lds[4 * 16];
+    const size_t off = blockIdx.y * stride;
+    x += off; ph += off; sh += off; r += off; s += off; t += off; rt += off;
+    using C = typename CT<T>::C;
+    const C ar = (C)sc->alpha[0], ai = (C)sc->alpha[1], wr = (C)sc->omega[0], wi = (C)sc->omega[1];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const auto xv = ldv(x[i]), pv = ldv(ph[i]), sv = ldv(sh[i]), s2 = ldv(s[i]), tv = ldv(t[i]);
+        stv(x[i], xv.x + (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y),
+            xv.y + (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x));
+        stv(r[i], s2.x - (wr * tv.x - wi * tv.y), s2.y - (wr * tv.y + wi * tv.x));
+        const auto rn = ldv(r[i]), rr = ldv(rt[i]);
+        v[0] += (double)rr.x * (double)rn.x + (double)rr.y * (double)rn.y;
+        v[1] += (double)rr.x * (double)rn.y - (double)rr.y * (double)rn.x;
+        v[2] += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+    }
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0) {
+        double *pr = partials + (size_t)blockIdx.y * 6 * pstride;
+#pragma unroll
+        for (int k = 0; k < 4; k++) pr[k * pstride + blockIdx.x] = v[k];
+    }
+}
+
 static dim3 blas_grid(size_t n, int nrhs = 1)
 {
     size_t b = (n + 255) / 256;
@@ -1089,6 +1150,22 @@ hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const voi
 {
     WCL_BY_PREC((k_bicg_xr<T><<<blas_grid(n, nrhs), 256, 0, st>>>(n, stride, WCL_V(x), WCL_CV(ph), WCL_CV(sh),
                                                                    WCL_V(r), WCL_CV(s), WCL_CV(t), sc)));
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr_dots(int prec, size_t n, void *x, const void *ph, const void *sh, void *r,
+                               const void *s, const void *t, const void *rt, const Scalars *sc, hipStream_t st,
+                               int nrhs, size_t stride, double *partials, int pstride, int *nparts)
+{
+    // at most RED_BLOCKS workgroups per right-hand side, so that the finaliser
+    // adds few partials
+    dim3 grid = blas_grid(n, nrhs);
+    if (grid.x > (unsigned)RED_BLOCKS) grid.x = RED_BLOCKS;
+    if ((int)grid.x > pstride) return hipErrorInvalidValue;
+    *nparts = (int)grid.x;
+    WCL_BY_PREC((k_bicg_xr_dots<T><<<grid, 256, 0, st>>>(n, stride, WCL_V(x), WCL_CV(ph), WCL_CV(sh), WCL_V(r),
+                                                          WCL_CV(s), WCL_CV(t), WCL_CV(rt), sc, partials,
+                                                          pstride)));
     return hipGetLastError();
 }
 
@@ -1166,54 +1243,64 @@ void hop_work(const HopLaunch &a, double *bytes, double *flops)
         b += spinor_site_bytes(a.spin_prec);
         f += 48.0;
     }
+    if (a.ndot) {   // fused reductions: the second vector and 96 flop per inner product
+        b += spinor_site_bytes(a.spin_prec);
+        f += a.ndot == 1 ? 96.0 : 144.0;
+    }
     *bytes = b * sites;
     *flops = f * sites;
 }
 
 // ---------------------------------------------------------------------------
-// Streaming ceilings for the roofline: a read-only pass (8 independent float4
-// loads in flight per thread, one float written per thread) and a copy.
-__global__ void __launch_bounds__(256) k_stream_read(const float4 *__restrict__ a, size_t n, float *out)
+// Streaming ceilings for the roofline.  Read: each workgroup streams one
+// contiguous chunk with 16 independent 16-byte non-temporal loads in flight
+// per thread (the fastest of a sweep over chunked / grid-stride order,
+// temporal / non-temporal loads, 4 / 8 / 16 loads in flight and 1024 ...
+// 32768 workgroups of 256 ... 1024 threads); one word written per thread.
+// Copy: the same order with 8 loads and 8 stores in flight.
+__global__ void __launch_bounds__(256) k_stream_read(const u32x4 *__restrict__ a, size_t n, size_t chunk, float *out)
 {
-    constexpr int U = 8;
-    float4 s = {0.f, 0.f, 0.f, 0.f};
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        float4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) v[u] = a[i + u * stride];
+    constexpr int U = 16;
+    u32x4 s = {0u, 0u, 0u, 0u};
+    const size_t base = (size_t)blockIdx.x * chunk, end = base + chunk < n ? base + chunk : n;
+    for (size_t i = base + threadIdx.x; i < end; i += U * blockDim.x) {
+        u32x4 v[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            s.x += v[u].x; s.y += v[u].y; s.z += v[u].z; s.w += v[u].w;
+            const size_t j = i + u * blockDim.x;
+            v[u] = j < end ? __builtin_nontemporal_load(a + j) : u32x4{0u, 0u, 0u, 0u};
         }
+#pragma unroll
+        for (int u = 0; u < U; u++) s ^= v[u];
     }
-    for (; i < n; i += stride) {
-        const float4 v = a[i];
-        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
-    }
-    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s.x + s.y + s.z + s.w;
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = __uint_as_float(s.x ^ s.y ^ s.z ^ s.w);
 }
 
-__global__ void __launch_bounds__(256) k_stream_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n)
+__global__ void __launch_bounds__(256) k_stream_copy(const u32x4 *__restrict__ a, u32x4 *__restrict__ b, size_t n,
+                                                    size_t chunk)
 {
-    constexpr int U = 4;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        float4 v[U];
+    constexpr int U = 8;
+    const size_t base = (size_t)blockIdx.x * chunk, end = base + chunk < n ? base + chunk : n;
+    for (size_t i = base + threadIdx.x; i < end; i += U * blockDim.x) {
+        u32x4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = a[i + u * stride];
+        for (int u = 0; u < U; u++) {
+            const size_t j = i + u * blockDim.x;
+            if (j < end) v[u] = __builtin_nontemporal_load(a + j);
+        }
 #pragma unroll
-        for (int u = 0; u < U; u++) b[i + u * stride] = v[u];
+        for (int u = 0; u < U; u++) {
+            const size_t j = i + u * blockDim.x;
+            if (j < end) __builtin_nontemporal_store(v[u], b + j);
+        }
     }
-    for (; i < n; i += stride) b[i] = a[i];
 }
 
 hipError_t launch_stream(int copy, const void *a, void *b, size_t n16, float *out, int blocks, hipStream_t st)
 {
-    if (copy) k_stream_copy<<<blocks, 256, 0, st>>>((const float4 *)a, (float4 *)b, n16);
-    else k_stream_read<<<blocks, 256, 0, st>>>((const float4 *)a, n16, out);
+    const size_t chunk = (n16 + blocks - 1) / blocks;
+    if (copy) k_stream_copy<<<blocks, 256, 0, st>>>((const u32x4 *)a, (u32x4 *)b, n16, chunk);
+    else k_stream_read<<<blocks, 256, 0, st>>>((const u32x4 *)a, n16, chunk, out);
     return hipGetLastError();
 }
 

@@ -59,13 +59,24 @@ struct HopLaunch {
     int depth;          // hops whose operands are in flight per thread (2, 3)
     int nontemporal;    // links / clover loaded non-temporally (single right-hand side only)
     int lds_stage;      // 1: stage each 128-site tile's input spinors in LDS (block 128, 4^4 tiles)
+    int tpw;            // consecutive site blocks per workgroup (0 or 1: one; at most 64)
     int rhs_per_thread; // 2 or 4: batched launches keep that many right-hand sides per thread
                         // (FP32 spinors, modes HOP / CLOV_H / XPAY); else one per workgroup
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
     LaunchEvents ev;           // timing events of the launch (null: untimed)
+    // fused reductions (mode XPAY, FP32 / FP16 spinors, one right-hand side per
+    // workgroup): ndot 1 writes the partials of <dotw, out> (terms 0, 1);
+    // ndot 2 those of <out, dotw> (terms 0, 1) and <out, out> (term 2), per
+    // workgroup at partials[rhs][term][block] (stride pstride)
+    int ndot;
+    const void *dotw;
+    double *partials;
+    int pstride;
 };
 
 hipError_t launch_hop(const HopLaunch &a, hipStream_t st);
+// workgroups per right-hand side of a hop launch (the partials of a fused reduction)
+int hop_parts(const HopLaunch &a);
 
 // Algorithmic HBM bytes and flops of one hop launch (per the operator's
 // definition: every link, the input spinor, the clover site and the output
@@ -133,7 +144,8 @@ struct Scalars {
 // right-hand side (slices `stride` complex numbers apart); partials hold
 // [nrhs][6][RED_BLOCKS] doubles.
 hipError_t launch_dots(int prec, size_t n, int npairs, const void *const *a, const void *const *b,
-                       double *partials, const Scalars *sc, hipStream_t st, int nrhs = 1, size_t stride = 0);
+                       double *partials, const Scalars *sc, hipStream_t st, int nrhs = 1, size_t stride = 0,
+                       int pstride = RED_BLOCKS);
 
 // BiCGStab building blocks (complex scalars taken from Scalars).
 enum BicgStep {
@@ -143,8 +155,11 @@ enum BicgStep {
     BICG_RHO = 3,        // rho_old = rho; rho = <rt, r>; r2 = |r|^2; done if r2 <= stop2 b2
     NORM_ONLY = 4,       // t[0] = |v|^2
 };
+// pstride: doubles between the terms of one right-hand side's partials (6
+// terms per right-hand side); nparts: partials per term to add.
 hipError_t launch_finalize(int step, int nterms, const double *partials, Scalars *sc, hipStream_t st,
-                           int nrhs = 1, const Scalars *gate = nullptr);
+                           int nrhs = 1, const Scalars *gate = nullptr, int pstride = RED_BLOCKS,
+                           int nparts = RED_BLOCKS);
 
 // p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
 hipError_t launch_bicg_p(int prec, size_t n, const void *r, void *p, const void *v, const Scalars *sc,
@@ -156,6 +171,12 @@ hipError_t launch_bicg_s(int prec, size_t n, const void *r, const void *v, void 
 hipError_t launch_bicg_xr(int prec, size_t n, void *x, const void *ph, const void *sh, void *r,
                           const void *s, const void *t, const Scalars *sc, hipStream_t st, int nrhs = 1,
                           size_t stride = 0);
+
+// the same with the partials of <rt, r>, <r, r> of the new r per workgroup
+// (terms 0..3 as for BICG_RHO); *nparts receives the workgroup count.
+hipError_t launch_bicg_xr_dots(int prec, size_t n, void *x, const void *ph, const void *sh, void *r,
+                               const void *s, const void *t, const void *rt, const Scalars *sc, hipStream_t st,
+                               int nrhs, size_t stride, double *partials, int pstride, int *nparts);
 
 // Generic complex axpby: y = a x + b y, a and b host constants.
 hipError_t launch_axpby(int prec, size_t n, double2 a, const void *x, double2 b, void *y, hipStream_t st);

@@ -49,6 +49,19 @@ class wcl_solve_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class wcl_tuning(ctypes.Structure):
+    _fields_ = [("hop_block", ctypes.c_int), ("hop_depth", ctypes.c_int), ("hop_xcd", ctypes.c_int),
+                ("hop_tiles", ctypes.c_int), ("rhs_per_thread", ctypes.c_int), ("use_ras", ctypes.c_int),
+                ("ras_overlap", ctypes.c_int), ("cached", ctypes.c_int), ("hop_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+TUNE_HOP, TUNE_BATCH, TUNE_SCHWARZ = 1, 2, 4
+
+
 class wcl_kstat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int), ("idle_launches", ctypes.c_int), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double), ("idle_ms", ctypes.c_double)]
@@ -94,6 +107,9 @@ def load():
     lib.wcl_set_tuning.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.wcl_autotune_hop.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip]
     lib.wcl_set_hop_staging.argtypes = [_vp, ctypes.c_int]
+    lib.wcl_set_hop_tiles.argtypes = [_vp, ctypes.c_int]
+    lib.wcl_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(wcl_solve_opts), ctypes.c_int,
+                                 ctypes.POINTER(wcl_tuning)]
     lib.wcl_set_compression.argtypes = [_vp, ctypes.c_int]
     lib.wcl_set_batch_tuning.argtypes = [_vp, ctypes.c_int]
     lib.wcl_bench_stream.argtypes = [_vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -229,6 +245,17 @@ def wcl_autotune_hop(h, prec, copies):
     return {"hop_block": best[0], "hop_depth": best[1], "hop_xcd": best[2]}
 
 
+def wcl_autotune(h, prec, nrhs, flags, b_ptr=None, opts=None):
+    t = wcl_tuning()
+    _check(load().wcl_autotune(h, int(prec), int(nrhs), _vp(b_ptr or 0),
+                               ctypes.byref(opts) if opts is not None else None, int(flags), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def wcl_set_hop_tiles(h, tiles):
+    _check(load().wcl_set_hop_tiles(h, int(tiles)))
+
+
 def wcl_set_hop_staging(h, enable):
     _check(load().wcl_set_hop_staging(h, int(enable)))
 
@@ -335,6 +362,19 @@ class Lattice:
     def bench_hop(self, prec=32, reps=100, copies=1, nrhs=1):
         self._sync_stream()
         return wcl_bench_hop(self.h, prec, reps, copies, nrhs)
+
+    def autotune(self, prec=32, nrhs=1, flags=TUNE_HOP, b=None, **opts):
+        """The project autotuner (wcl_autotune); opts as for solve()."""
+        o = None
+        bp = None
+        if b is not None:
+            b, nrhs = self._spinors(b)
+            bp = b.data_ptr()
+            o = wcl_default_opts()
+            for k, v in opts.items():
+                setattr(o, k, v)
+        self._sync_stream()
+        return wcl_autotune(self.h, prec, nrhs, flags, bp, o)
 
     def bench_clover(self, prec=32, reps=100, copies=1):
         self._sync_stream()

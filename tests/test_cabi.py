@@ -41,7 +41,7 @@ def _struct_fields(name):
     return [m.group(2) for m in re.finditer(r"\b(int|double|const double\s*\*)\s*([a-z_0-9]+)\s*;", body)]
 
 
-@pytest.mark.parametrize("name", ["wcl_solve_opts", "wcl_solve_info", "wcl_kstat"])
+@pytest.mark.parametrize("name", ["wcl_solve_opts", "wcl_solve_info", "wcl_kstat", "wcl_tuning"])
 def test_binding_structs_match_the_header(name):
     """The ctypes structures list the header's fields in the header's order."""
     from paper_1612_06556_amd import wcl

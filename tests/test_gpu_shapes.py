@@ -2,9 +2,9 @@
 can select, against the FP64 oracle (through the C ABI).
 
 wcl_autotune_hop chooses among 64/128/256 threads per workgroup, pipeline
-depth 2 or 3 and XCD-aware or plain workgroup order; wcl_set_tuning adds
-non-temporal operator loads and wcl_set_hop_staging the LDS copy of the input
-spinors.  Each shape is a different kernel instantiation (for full or two-row
+depth 2 or 3, XCD-aware or plain workgroup order and 1/2/4/8 site blocks per
+workgroup; wcl_set_tuning adds non-temporal operator loads and
+wcl_set_hop_staging the LDS copy of the input spinors.  Each shape is a different kernel instantiation (for full or two-row
 links, FP32 or FP16 storage), so each is compared with the oracle: D, the
 hopping term H and the Schur operator Dhat, norm-wise (FP32 1e-6, FP16 3e-3)
 and site by site (largest site error over the rms site norm <= 10x the
@@ -25,7 +25,9 @@ CASES = [  # dims, tbc, kappa, csw, seed, tile
     ((4, 6, 8, 4), -1, 0.125, 1.3, 7, None),          # 2^4 tiles, ragged last workgroup
     ((24, 24, 24, 32), -1, 0.126, 1.0, 1003, None),   # the benchmark's lattice
 ]
-SHAPES = list(itertools.product((64, 128, 256), (2, 3), (0, 1), (0, 1), (1, 0)))  # block, depth, xcd, nt, stage
+# block, depth, xcd, nt, stage, site blocks per workgroup
+SHAPES = [s + (1,) for s in itertools.product((64, 128, 256), (2, 3), (0, 1), (0, 1), (1, 0))]
+SHAPES += [s + (t,) for s in itertools.product((64, 128, 256), (2, 3), (0, 1), (0, 1), (1,)) for t in (2, 4, 8)]
 
 _refs = {}
 
@@ -58,19 +60,22 @@ def test_every_hop_shape(case, compress):
     lat.set_compression(compress)
     try:
         for prec in (32, 16):
-            for block, depth, xcd, nt, stage in SHAPES:
+            for block, depth, xcd, nt, stage, tpw in SHAPES:
                 wcl.wcl_set_tuning(lat.h, block, depth, xcd, nt)
                 wcl.wcl_set_hop_staging(lat.h, stage)
+                wcl.wcl_set_hop_tiles(lat.h, tpw)
                 outs = (to_host(lat.apply(g, prec=prec)), to_host(lat.apply_op(wcl.OP_HOP, g, prec=prec)),
                         to_host(lat.apply_op(wcl.OP_SCHUR, ge, prec=prec)))
                 for name, out, ref in zip(("D", "H", "Dhat"), outs, (ref_d, ref_h, ref_s)):
                     e, es = rel(out, ref), site_err(out, ref)
                     tag = (prec, name)
                     worst[tag] = max(worst.get(tag, (0.0, 0.0)), (e, es))
-                    assert e <= TOL[prec] and es <= 10 * TOL[prec], (prec, block, depth, xcd, nt, stage, name, e, es)
+                    assert e <= TOL[prec] and es <= 10 * TOL[prec], (prec, block, depth, xcd, nt, stage, tpw, name,
+                                                                     e, es)
     finally:
         wcl.wcl_set_tuning(lat.h, 256, 2, 1, 0)
         wcl.wcl_set_hop_staging(lat.h, 1)
+        wcl.wcl_set_hop_tiles(lat.h, 1)
         lat.set_compression(0)
     for tag, (e, es) in sorted(worst.items()):
         print(f"dims={dims} compress={compress} prec={tag[0]} {tag[1]}: worst rel {e:.2e}, worst site {es:.2e} "
@@ -114,3 +119,39 @@ def test_bench_hop_batched(nrhs):
         lat.bench_hop(32, 5, 2, nrhs=65)
     psi = synth.gaussian_spinor(dims, 41)
     assert rel(to_host(lat.apply(to_gpu(psi), prec=32)), orc.D(psi)) <= 1e-6
+
+
+def test_project_autotuner():
+    """wcl_autotune: the hop shape, the batched right-hand sides per thread and
+    the Schwarz choice (by measured time to solution) come from the parity-tested
+    candidate sets; the result is cached per (lattice, precision, nrhs, flags);
+    the operator and a solve with the chosen recipe still match the oracle."""
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 9, (4, 4, 4, 4))
+    try:
+        t = lat.autotune(32, 1, wcl.TUNE_HOP)
+        assert t["cached"] == 0 and (t["hop_block"], t["hop_depth"], t["hop_xcd"], t["hop_tiles"]) in \
+            {(s[0], s[1], s[2], s[5]) for s in SHAPES}
+        assert lat.autotune(32, 1, wcl.TUNE_HOP)["cached"] == 1
+        tb = lat.autotune(16, 4, wcl.TUNE_HOP | wcl.TUNE_BATCH)
+        assert tb["rhs_per_thread"] in (1, 2, 4)
+        psi = synth.gaussian_spinor(dims, 81)
+        for prec in (32, 16):
+            out = to_host(lat.apply(to_gpu(psi), prec=prec))
+            assert rel(out, orc.D(psi)) <= TOL[prec]
+        b = synth.gaussian_spinor(dims, 82)
+        opts = dict(tol=1e-10, inner_tol=1e-1, use_ras=1, ras_overlap=1)
+        ts = lat.autotune(32, 1, wcl.TUNE_SCHWARZ, b=to_gpu(b), **opts)
+        print("autotuned", t, tb, ts, flush=True)
+        assert (ts["use_ras"], ts["ras_overlap"]) in {(1, 1), (1, 0), (0, 1)} and ts["solve_ms"] > 0
+        x, info, rc = lat.solve(to_gpu(b), **dict(opts, use_ras=ts["use_ras"], ras_overlap=ts["ras_overlap"]))
+        xr, _ = orc.bicgstab_eo(b, 1e-13, 20000)
+        assert rc == 0 and rel(to_host(x), xr) <= 1e-8
+        with pytest.raises(wcl.WclError):
+            lat.autotune(32, 1, wcl.TUNE_SCHWARZ)   # needs a source and options
+    finally:
+        wcl.wcl_set_tuning(lat.h, 256, 2, 1, 0)
+        wcl.wcl_set_hop_tiles(lat.h, 1)
+        wcl.wcl_set_batch_tuning(lat.h, 1)
+        lat.set_ras(1, 4, 0, 0)
