@@ -41,9 +41,9 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 # FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
-    "ras": {"fetch_kib": 2143605.3, "fetch_scale": 1048576 / 524307.875, "write_kib": 82944.6,
-            "write_scale": 1.0, "sources": ("ras.hip", "wcl_common.h"),
-            "sha256": "a329342c4014a2e4eba0048b401fbd9f2c55067ccc3fc9bd9dafc920bb1379a5",
+    "ras": {"fetch_kib": 2145032.0, "fetch_scale": 1048576 / 524314.6875, "write_kib": 82944.3,
+            "write_scale": 1.0, "sources": ("ras.hip", "ras_dev.h", "wcl_common.h"),
+            "sha256": "fc6ffd7f4824b2115a0f6e00724937f1d17ac0f335c0dc8af984a9a97a7d2187",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
@@ -162,10 +162,15 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     the plain FP64 solve."""
     out = {}
     hop, clov = {}, {}
+    shapes = {}
     for comp in (0, 1):
         lat.set_compression(comp)
         for prec in (32, 16):
             link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
+            # each storage tier with its own autotuned launch shape
+            t = lat.autotune(prec, 1, wcl.TUNE_HOP)
+            shapes[f"fp{prec}{'_r12' if comp else ''}"] = {k: t[k] for k in ("hop_block", "hop_depth", "hop_xcd",
+                                                                           "hop_tiles")}
             for copies, tag in ((4, "cold"), (1, "hot")):
                 ms = _median_ms(lambda: lat.bench_hop(prec, 1000, copies))
                 name = f"fp{prec}{'_r12' if comp else ''}_{tag}"
@@ -175,7 +180,7 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                     clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
     # single-use (cold) calls with non-temporal link and clover loads
     lat.set_compression(0)
-    tune = wcl.wcl_autotune_hop(lat.h, 32, 4)
+    tune = lat.autotune(32, 1, wcl.TUNE_HOP)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 1)
     hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 1000, 4)), Vh, 1320, 768)
     lat.set_compression(1)
@@ -189,8 +194,10 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
         ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
         hop[f"fp{prec}_r12_cold_unstaged"] = _rate(ms, Vh, 1320, 8 * (48 if prec == 32 else 24) + 192)
     wcl.wcl_set_hop_staging(lat.h, 1)
-    wcl.wcl_autotune_hop(lat.h, 32, 4)
+    lat.set_compression(1)
+    lat.autotune(32, 1, wcl.TUNE_HOP)
     out["hop_standalone"] = hop
+    out["hop_standalone_shapes"] = shapes
     out["clover_standalone"] = clov
     # measured streaming ceilings of this device (library kernels, 2 GiB buffers)
     read_gbs, copy_gbs = wcl.wcl_bench_stream(lat.h, 2048, 10)

@@ -107,8 +107,13 @@ WCL_D void ras_compute(const RasStage<SL> &st, const float2 *src, cplx<float> ac
         psi[c] = {v.x, v.y};
     }
     project<MU, S, float>(psi, hh);
+    // the weight carries the t boundary sign; on other directions a cut hop
+    // already has a zero link, except with two-row FP16 links, which are
+    // loaded for every hop
+    if constexpr (MU == 3 || std::is_same<SL, R12h>::value) {
 #pragma unroll
-    for (int k = 0; k < 6; k++) hh[k] = st.w * hh[k];
+        for (int k = 0; k < 6; k++) hh[k] = st.w * hh[k];
+    }
     expand_link<SL, float>(st.u, u);
     if (FWD) su3_mul(u, hh, uh);
     else su3_dag_mul(u, hh, uh);
