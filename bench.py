@@ -263,6 +263,7 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                                 "solve_ms": round(ts["solve_ms"], 2),
                                 "candidates": "the step's recipe (overlap 1), overlap 0, no Schwarz"}
     out["batch12_32x32x32x64"] = batch12(opts, torch, synth, wcl)
+    out["lattice_sweep"] = lattice_sweep(opts, torch, synth, wcl)
     out["differentiation_16x16x16x32"] = backward_timing(torch, synth, wcl)
     # setup: gauge ingest + casts + SU(3) check + two-row copies, then clover build and inversion
     gU = torch.from_numpy(U).cuda()
@@ -279,6 +280,38 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
         ts_p.append(time.perf_counter() - t2)
     out["setup_ms"] = {"set_gauge": round(float(np.median(ts_g)) * 1e3, 3),
                        "set_params_clover_build": round(float(np.median(ts_p)) * 1e3, 3)}
+    return out
+
+
+def lattice_sweep(opts, torch, synth, wcl):
+    """Time to 1e-10 against lattice size (the 24^3x32 row is the step's own
+    time_to_solution): the paper's method (FP32 RAS inner), the fastest tier
+    (no Schwarz, FP16 links and vectors) and plain FP64 on the even/odd
+    system; two-row links, autotuned hop shape, one warm run then one timed."""
+    out = {}
+    for dims, kappa, seed in (((8, 8, 8, 8), 0.12, 1001), ((16, 16, 16, 32), 0.125, 1002),
+                              ((32, 32, 32, 64), 0.126, 1004)):
+        U = torch.from_numpy(synth.su3_field(dims, seed)).cuda()
+        b = torch.from_numpy(synth.gaussian_spinor(dims, seed + 1000)).cuda()
+        lat = wcl.Lattice(dims, -1)
+        lat.set_compression(1)
+        lat.set_gauge(U)
+        lat.set_params(kappa, CSW)
+        lat.autotune(32, 1, wcl.TUNE_HOP)
+        row = {"kappa": kappa}
+        for name, kw in (("mixed_ras_fp32", opts),
+                         ("mixed_noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16)),
+                         ("plain_fp64_eo", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64_EO, max_outer=20000))):
+            lat.solve(b, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info, _ = lat.solve(b, **kw)
+            torch.cuda.synchronize()
+            row[name] = {"ms": round((time.perf_counter() - t1) * 1e3, 2), "outer": info["outer_iters"],
+                         "inner": info["inner_iters_total"], "true_relres": info["true_relres"]}
+        out["x".join(map(str, dims))] = row
+        lat.close()
+        del U, b
     return out
 
 

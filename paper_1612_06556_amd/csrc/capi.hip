@@ -1425,8 +1425,15 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
                 for (int k = 0; k < n; k++) info[k].inner_iters_total += final_[k] ? 0 : it_inner[k];
                 ph = w.ph;
             }
-            CHK(apply_A(c, d, w, ph, w.v, sc));
-            {
+            // on the even/odd system the reductions ride in the Schur operator's
+            // second half and the x/r update, as in the inner solver
+            const bool fused = d.eo && (c->hop_rhs == 1 || n == 1);
+            int np = 0;
+            if (fused) {
+                CHK(schur_dot(c, P64, P64, ph, w.v, w.o, sc, n, 1, w.rt, &np));
+                HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+            } else {
+                CHK(apply_A(c, d, w, ph, w.v, sc));
                 const void *a[1] = {w.rt}, *b[1] = {w.v};
                 HIPCHK(launch_dots(P64, m, 1, a, b, c->partials, sc, c->st, n, m, c->pstride));
                 HIPCHK(launch_finalize(BICG_ALPHA, 2, c->partials, sc, c->st, n, nullptr, c->pstride));
@@ -1437,17 +1444,25 @@ int bicgstab_driver(wcl_ctx *c, const Driver &d, const wcl_solve_opts &o, const 
                 for (int k = 0; k < n; k++) info[k].inner_iters_total += final_[k] ? 0 : it_inner[k];
                 sh = w.sh;
             }
-            CHK(apply_A(c, d, w, sh, w.t, sc));
-            {
-                const void *a[2] = {w.t, w.t}, *b[2] = {w.s, w.t};
-                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
-                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
-            }
-            HIPCHK(launch_bicg_xr(P64, m, d.x, ph, sh, w.r, w.s, w.t, sc, c->st, n, m));
-            {
-                const void *a[2] = {w.rt, w.r}, *b[2] = {w.r, w.r};
-                HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
-                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
+            if (fused) {
+                CHK(schur_dot(c, P64, P64, sh, w.t, w.o, sc, n, 2, w.s, &np));
+                HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+                HIPCHK(launch_bicg_xr_dots(P64, m, d.x, ph, sh, w.r, w.s, w.t, w.rt, sc, c->st, n, m, c->partials,
+                                           c->pstride, &np));
+                HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride, np));
+            } else {
+                CHK(apply_A(c, d, w, sh, w.t, sc));
+                {
+                    const void *a[2] = {w.t, w.t}, *b[2] = {w.s, w.t};
+                    HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+                    HIPCHK(launch_finalize(BICG_OMEGA, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
+                }
+                HIPCHK(launch_bicg_xr(P64, m, d.x, ph, sh, w.r, w.s, w.t, sc, c->st, n, m));
+                {
+                    const void *a[2] = {w.rt, w.r}, *b[2] = {w.r, w.r};
+                    HIPCHK(launch_dots(P64, m, 2, a, b, c->partials, sc, c->st, n, m, c->pstride));
+                    HIPCHK(launch_finalize(BICG_RHO, 4, c->partials, sc, c->st, n, nullptr, c->pstride));
+                }
             }
         }
         iter += chunk;

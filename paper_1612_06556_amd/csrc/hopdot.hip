@@ -71,6 +71,7 @@ hipError_t launch_hop_dot(const HopLaunch &L, const HopArgs &a, dim3 grid, dim3 
 {
     if (L.mode != XPAY || L.dagger || (L.ndot != 1 && L.ndot != 2) || !L.dotw || !L.partials) return hipErrorInvalidValue;
     if ((int)(grid.x / a.nrhs) > L.pstride) return hipErrorInvalidValue;
+    if (L.link_prec == P64 && L.spin_prec == P64) return hop_dot_n<double, double>(L, a, grid, block, st);
     if (L.link_prec == P32 && L.spin_prec == P32) return hop_dot_n<float, float>(L, a, grid, block, st);
     if (L.link_prec == P16 && L.spin_prec == P32) return hop_dot_n<__half, float>(L, a, grid, block, st);
     if (L.link_prec == P16 && L.spin_prec == P16) return hop_dot_n<__half, __half>(L, a, grid, block, st);

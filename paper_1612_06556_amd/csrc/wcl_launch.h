@@ -64,7 +64,7 @@ struct HopLaunch {
                         // (FP32 spinors, modes HOP / CLOV_H / XPAY); else one per workgroup
     const struct Scalars *sc;  // if non-null, the launch is a no-op once sc->done
     LaunchEvents ev;           // timing events of the launch (null: untimed)
-    // fused reductions (mode XPAY, FP32 / FP16 spinors, one right-hand side per
+    // fused reductions (mode XPAY, FP64 / FP32 / FP16 spinors, one right-hand side per
     // workgroup): ndot 1 writes the partials of <dotw, out> (terms 0, 1);
     // ndot 2 those of <out, dotw> (terms 0, 1) and <out, out> (term 2), per
     // workgroup at partials[rhs][term][block] (stride pstride)
