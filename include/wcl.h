@@ -67,8 +67,10 @@ enum { WCL_PREC64 = 64, WCL_PREC32 = 32, WCL_PREC16 = 16 };
  * (each even and dividing dims[mu]); NULL picks 4^4 when it divides the
  * lattice, else 2^4.  t_bc = +1 periodic, -1 antiperiodic in time.
  * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
- * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL;
- * WCL_ENOMEM / WCL_EHIP when the context's first device buffers fail. */
+ * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL
+ * (also for more than 7,456,540 sites: fields are addressed with 32-bit byte
+ * offsets, and the FP64 links take 576 bytes a site); WCL_ENOMEM / WCL_EHIP
+ * when the context's first device buffers fail. */
 int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream, wcl_ctx **out);
 /* Switch the stream every later call of this context is ordered on. */
 int wcl_set_stream(wcl_ctx *ctx, void *hip_stream);

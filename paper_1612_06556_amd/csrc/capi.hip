@@ -68,6 +68,7 @@ struct wcl_ctx {
     int device = 0;
     void *U64 = nullptr, *U32 = nullptr, *U16 = nullptr;
     void *U32c = nullptr, *U16c = nullptr;  // two-row links (built when compression is on)
+    void *U32s = nullptr;                   // per-site copy of U32c (the fused Schwarz kernel's)
     int compress = 0;                       // FP32/FP16 tiers read the two-row links
     void *T64 = nullptr, *Ti64 = nullptr, *T32 = nullptr, *Ti32 = nullptr, *T16 = nullptr, *Ti16 = nullptr;
     int *info = nullptr;
@@ -580,6 +581,7 @@ int build_compressed(wcl_ctx *c)
     if (!c->U32c) {
         CHK(alloc(&c->U32c, link_bytes_c(P32C, Vh)));
         CHK(alloc(&c->U16c, link_bytes_c(P16C, Vh)));
+        CHK(alloc(&c->U32s, link_bytes_c(P32C, Vh)));
     }
     const int nb = 256;
     void *part;
@@ -596,7 +598,7 @@ int build_compressed(wcl_ctx *c)
         snprintf(msg, sizeof msg, "two-row link storage needs SU(3) links: largest defect %.3e > %.1e", m, SU3_TOL);
         return fail(WCL_EINVAL, msg);
     }
-    HIPCHK(launch_compress_links(c->g, c->U64, c->U32c, c->U16c, c->st));
+    HIPCHK(launch_compress_links(c->g, c->U64, c->U32c, c->U16c, c->U32s, c->st));
     return WCL_OK;
 }
 
@@ -626,7 +628,9 @@ int wcl_create(const int dims[4], int t_bc, const int tile[4], void *hip_stream,
     for (int mu = 0; mu < 4; mu++)
         if (B[mu] < 2 || (B[mu] & 1) || dims[mu] % B[mu]) return fail(WCL_EINVAL, "tile extents must be even and divide the lattice");
     const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    if (V > (1ll << 30)) return fail(WCL_EINVAL, "lattice too large");
+    // every field is addressed with 32-bit byte offsets; the largest, the FP64
+    // links (576 bytes a site), must stay below 4 GiB
+    if (V * 576ll >= (1ll << 32)) return fail(WCL_EINVAL, "lattice too large (at most 7456540 sites)");
     wcl_ctx *c = new wcl_ctx();
     Geom &g = c->g;
     for (int mu = 0; mu < 4; mu++) {
@@ -678,7 +682,7 @@ int wcl_destroy(wcl_ctx *c)
 {
     if (!c) return WCL_OK;
     (void)hipStreamSynchronize(c->st);
-    void *ptrs[] = {c->U64, c->U32, c->U16, c->U32c, c->U16c, c->T64, c->Ti64, c->T32, c->Ti32, c->T16, c->Ti16, c->info,
+    void *ptrs[] = {c->U64, c->U32, c->U16, c->U32c, c->U16c, c->U32s, c->T64, c->Ti64, c->T32, c->Ti32, c->T16, c->Ti16, c->info,
                     c->partials, c->sc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -873,6 +877,7 @@ int wcl_apply_op(wcl_ctx *c, int op, const double *in, double *out, int nrhs, in
             R.in = par(a, sp, Vh, 0);
             R.out = par(b, sp, Vh, 0);
             R.links = links_for(c, R.link_prec);
+            R.links_site = c->U32s;
             R.clov_inv = clovinv_for(c, lp);
             R.kappa2 = (float)(c->kappa * c->kappa);
             R.sc = nullptr;
@@ -1066,6 +1071,7 @@ int inner_iteration(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, Scalars *sc, in
         R.jacobi = c->ras_solver == WCL_RAS_JACOBI;
         R.link_prec = eff_lprec(c, lp);
         R.links = links_for(c, R.link_prec);
+        R.links_site = c->U32s;
         R.clov_inv = clovinv_for(c, lp);
         R.kappa2 = (float)(c->kappa * c->kappa);
         R.sc = sc;
@@ -1154,6 +1160,7 @@ int inner_solve(wcl_ctx *c, const InnerCfg &cfg, SolveWs &w, const void *in64, v
         P.link_prec = eff_lprec(c, cfg.lprec);
         P.vec_prec = vp;
         P.links = links_for(c, P.link_prec);
+        P.links_site = c->U32s;
         P.clov_inv = clovinv_for(c, cfg.lprec);
         P.kappa2 = c->kappa * c->kappa;
         P.use_ras = cfg.ras ? 1 : 0;

@@ -105,7 +105,7 @@ __global__ void k_ingest_gauge(Geom g, const double2 *__restrict__ canon, void *
 }
 
 // Two-row (12-real) FP32 and FP16 copies of the FP64 links.
-__global__ void k_compress_links(Geom g, const void *u64, void *u32c, void *u16c)
+__global__ void k_compress_links(Geom g, const void *u64, void *u32c, void *u16c, void *u32s)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 8 * g.Vh) return;
@@ -114,11 +114,12 @@ __global__ void k_compress_links(Geom g, const void *u64, void *u32c, void *u16c
     load_link<double, double>(u64, mp >> 1, mp & 1, h, g.Vh, u);
     store_link<R12f, double>(u32c, mp >> 1, mp & 1, h, g.Vh, u);
     store_link<R12h, double>(u16c, mp >> 1, mp & 1, h, g.Vh, u);
+    store_link_site<double>(u32s, mp >> 1, mp & 1, h, g.Vh, u);
 }
 
-hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, hipStream_t st)
+hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, void *u32s, hipStream_t st)
 {
-    k_compress_links<<<(8 * g.Vh + 255) / 256, 256, 0, st>>>(g, u64, u32c, u16c);
+    k_compress_links<<<(8 * g.Vh + 255) / 256, 256, 0, st>>>(g, u64, u32c, u16c, u32s);
     return hipGetLastError();
 }
 

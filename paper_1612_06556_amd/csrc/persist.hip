@@ -445,6 +445,7 @@ hipError_t launch_persist(const PersistLaunch &L, hipStream_t st)
             ne *= L.g->B[mu] + 2 * L.overlap;
         }
         if (ne / 2 > 648 || L.jacobi) return hipErrorInvalidValue;
+        if (L.link_prec == P32C && !L.links_site) return hipErrorInvalidValue;
         for (int half = 0; half < 2; half++) {
             RasArgs &r = a.ra[half];
             r.g = *L.g;
@@ -452,7 +453,7 @@ hipError_t launch_persist(const PersistLaunch &L, hipStream_t st)
             r.iters = L.iters;
             r.in = half ? L.s : L.p;
             r.out = half ? L.sh : L.ph;
-            r.links = L.links;
+            r.links = L.link_prec == P32C ? L.links_site : L.links;
             r.clov_inv = L.clov_inv;
             r.kappa2 = (float)L.kappa2;
             r.sc = nullptr;

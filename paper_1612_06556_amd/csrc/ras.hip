@@ -85,7 +85,9 @@ hipError_t launch_ras(const RasLaunch &L, hipStream_t st)
     a.iters = L.iters;
     a.in = L.in;
     a.out = L.out;
-    a.links = L.links;
+    // the two-row FP32 links are read from their per-site copy
+    if (L.link_prec == P32C && !L.links_site) return hipErrorInvalidValue;
+    a.links = L.link_prec == P32C ? L.links_site : L.links;
     a.clov_inv = L.clov_inv;
     a.kappa2 = L.kappa2;
     a.sc = L.sc;

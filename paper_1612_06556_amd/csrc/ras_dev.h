@@ -81,17 +81,11 @@ WCL_D void ras_load(const void *links, int q, const RasSite &S, uint32_t Vh, uin
     if (!in) ln = t;                       // any valid site; its weight is 0
     uint32_t gl = FWD ? S.g : (uint32_t)gnb[ln];
     ras_fence(acc, ln, gl);
-    // A cut hop fetches no link (its lanes are masked off): zero link,
-    // weight 0.  For the two-row FP16 links (24 bytes) the masked form
-    // measured slower, and they are loaded for every hop.
-    if constexpr (std::is_same<SL, R12h>::value) {
-        load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
-    } else {
-        if (in) load_link_raw<SL>(links, MU, FWD ? q : 1 - q, gl, Vh, st.u);
-        else st.u = LinkRaw<SL>{};
-    }
+    // a cut hop reads a zero link (out-of-range buffer offsets: no memory
+    // traffic, no branch)
+    load_link_raw_or_zero<SL>(field_rsrc(links), MU, FWD ? q : 1 - q, gl, in, Vh, st.u);
     st.ln = ln;
-    st.w = in ? (MU == 3 ? (FWD ? S.sf : S.sb) : 1.f) : 0.f;
+    st.w = MU == 3 ? (FWD ? S.sf : S.sb) : 1.f;   // used on t hops only
 }
 
 template <typename SL, int K, int NE>
@@ -107,10 +101,8 @@ WCL_D void ras_compute(const RasStage<SL> &st, const float2 *src, cplx<float> ac
         psi[c] = {v.x, v.y};
     }
     project<MU, S, float>(psi, hh);
-    // the weight carries the t boundary sign; on other directions a cut hop
-    // already has a zero link, except with two-row FP16 links, which are
-    // loaded for every hop
-    if constexpr (MU == 3 || std::is_same<SL, R12h>::value) {
+    // the weight carries the t boundary sign (a cut hop has a zero link)
+    if constexpr (MU == 3) {
 #pragma unroll
         for (int k = 0; k < 6; k++) hh[k] = st.w * hh[k];
     }

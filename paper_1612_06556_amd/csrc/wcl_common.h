@@ -388,6 +388,78 @@ WCL_D void load_link_raw(const void *base, int mu, int p, uint32_t h, uint32_t V
     }
 }
 
+// A link load that reads zero where `in` is false, without a branch: the
+// field is addressed through a buffer resource of 2 GiB (every FP32 / FP16
+// link field is smaller: the FP64 one is below 4 GiB), and a cut lane's
+// offset is moved to 2 GiB or more, where the load reads zero and touches no
+// memory.  Being unconditional, the loads also keep the compiler's wait
+// counts exact in a software pipeline (a load under a branch turns each
+// later wait for it into a wait for every load in flight).
+WCL_D __amdgpu_buffer_rsrc_t field_rsrc(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)0x80000000u, 0x00020000);
+}
+template <typename T>
+WCL_D T ldb(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    T r;
+    if constexpr (sizeof(T) == 16) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        __builtin_memcpy(&r, &v, 16);
+    } else if constexpr (sizeof(T) == 8) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        __builtin_memcpy(&r, &v, 8);
+    } else {
+        const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        __builtin_memcpy(&r, &v, 4);
+    }
+    return r;
+}
+
+// R12f: from the per-site copy (store_link_site).
+template <typename S>
+WCL_D void load_link_raw_or_zero(__amdgpu_buffer_rsrc_t rs, int mu, int p, uint32_t h, bool in, uint32_t Vh,
+                                 LinkRaw<S> &r)
+{
+    constexpr uint32_t OUT = 0x80000000u;
+    const uint32_t mp = (uint32_t)(mu * 2 + p);
+    const uint32_t o16 = in ? h * 16u : OUT, o8 = in ? h * 8u : OUT, o4 = in ? h * 4u : OUT;
+    if constexpr (std::is_same<S, R12f>::value) {
+        // the per-site copy (store_link_site)
+        const uint32_t o48 = in ? (mp * Vh + h) * 48u : OUT;
+#pragma unroll
+        for (uint32_t k = 0; k < 3; k++) r.v[k] = ldb<float4>(rs, o48 + k * 16u);
+    } else if constexpr (std::is_same<S, R12h>::value) {
+        r.v = ldb<uint4>(rs, mp * Vh * 16u + o16);
+        r.w = ldb<uint2>(rs, 8u * Vh * 16u + mp * Vh * 8u + o8);
+    } else if constexpr (sizeof(S) == 8) {
+#pragma unroll
+        for (uint32_t i = 0; i < 9; i++) r.v[i] = ldb<double2>(rs, (mp * 9 + i) * Vh * 16u + o16);
+    } else if constexpr (sizeof(S) == 4) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) r.v[k] = ldb<float4>(rs, (mp * 4 + k) * Vh * 16u + o16);
+        r.w = ldb<float2>(rs, 32u * Vh * 16u + mp * Vh * 8u + o8);
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < 2; k++) r.v[k] = ldb<uint4>(rs, (mp * 2 + k) * Vh * 16u + o16);
+        r.w = ldb<uint32_t>(rs, 16u * Vh * 16u + mp * Vh * 4u + o4);
+    }
+}
+
+// Per-site copy of the two-row FP32 links, [mu][parity][Vh][12 reals] (48
+// contiguous bytes a link): the fused Schwarz kernel gathers the links of
+// scattered block sites, and one link then spans one or two cache lines
+// instead of three partly used ones.
+template <typename R>
+WCL_D void store_link_site(void *base, int mu, int p, uint32_t h, uint32_t Vh, const cplx<R> u[9])
+{
+    const uint32_t mp = (uint32_t)(mu * 2 + p);
+#pragma unroll
+    for (uint32_t k = 0; k < 3; k++)
+        stf(base, (mp * Vh + h) * 48u + k * 16u,
+            make_float4((float)u[2 * k].re, (float)u[2 * k].im, (float)u[2 * k + 1].re, (float)u[2 * k + 1].im));
+}
+
 template <typename S, typename R>
 WCL_D void expand_link(const LinkRaw<S> &r, cplx<R> u[9])
 {

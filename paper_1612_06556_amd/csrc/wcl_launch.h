@@ -98,8 +98,10 @@ hipError_t launch_unpack_spinor(const Geom &g, const void *eo, double *canon, hi
 // Canonical U [V][4][3][3] -> internal link fields (any null pointer skipped).
 hipError_t launch_ingest_gauge(const Geom &g, const double *canon, void *u64, void *u32, void *u16,
                                hipStream_t st);
-// FP64 links -> two-row FP32 (P32C) and FP16 (P16C) link fields.
-hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, hipStream_t st);
+// FP64 links -> two-row FP32 (P32C) and FP16 (P16C) link fields, and the
+// per-site copy of the two-row FP32 links read by the fused Schwarz kernel.
+hipError_t launch_compress_links(const Geom &g, const void *u64, void *u32c, void *u16c, void *u32s,
+                                 hipStream_t st);
 // Per-workgroup maxima of the SU(3) defect of the FP64 links (|row2 -
 // conj(row0 x row1)|, |row norm - 1|, |<row0, row1>|) into partial[nblocks].
 hipError_t launch_su3_check(const Geom &g, const void *u64, double *partial, int nblocks, hipStream_t st);
@@ -192,6 +194,7 @@ struct RasLaunch {
     const void *in;      // even field, FP32 (or FP16 when vec_prec == P16)
     void *out;           // even field, same storage
     const void *links;
+    const void *links_site;   // two-row FP32 links per site (P32C, fused kernel), else unused
     const void *clov_inv;
     float kappa2;
     const Scalars *sc;   // may be null; per right-hand side, skips when done
@@ -219,6 +222,7 @@ struct PersistLaunch {
     const Geom *g;
     int link_prec, vec_prec;
     const void *links, *clov_inv;
+    const void *links_site;   // per-site two-row FP32 links of the Schwarz phases (P32C)
     double kappa2;
     int use_ras, overlap, iters;
     bool jacobi;

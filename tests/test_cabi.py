@@ -63,3 +63,16 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_create_refuses_fields_beyond_32bit_offsets():
+    """Fields are addressed with 32-bit byte offsets: a lattice whose FP64
+    links would reach 4 GiB (576 bytes a site) is refused before anything is
+    allocated."""
+    from paper_1612_06556_amd import wcl
+    lib = wcl.load()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(48, 48, 48, 96)   # 10,616,832 sites
+    rc = lib.wcl_create(dims, -1, None, None, ctypes.byref(h))
+    assert rc == wcl.WCL_EINVAL and not h.value
+    assert b"too large" in lib.wcl_last_error()
