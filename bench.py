@@ -37,13 +37,13 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 
 # Traffic of the RAS kernel from rocprofv3 counters over the bench step:
 # FETCH_SIZE and WRITE_SIZE per working dispatch (KiB), each scaled by what it
-# reads for a 1 GiB device copy (FETCH 524308.1 KiB -> x2.0, WRITE x1.0).
+# reads for a 1 GiB device copy (FETCH 524315.3 KiB -> x2.0, WRITE x1.0).
 # FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
-    "ras": {"fetch_kib": 2145032.0, "fetch_scale": 1048576 / 524314.6875, "write_kib": 82944.3,
+    "ras": {"fetch_kib": 1835288.4, "fetch_scale": 1048576 / 524315.3125, "write_kib": 82944.2,
             "write_scale": 1.0, "sources": ("ras.hip", "ras_dev.h", "wcl_common.h"),
-            "sha256": "fc6ffd7f4824b2115a0f6e00724937f1d17ac0f335c0dc8af984a9a97a7d2187",
+            "sha256": "bd835b034312427ba7e38d418ba00be9dc51c0c868a53c6fbf5a1b5679a85c13",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
