@@ -91,10 +91,14 @@ int wcl_set_params(wcl_ctx *ctx, double kappa, double csw);
 
 /* Two-row (12-real) link storage for the FP32 and FP16 tiers (enable 1) or
  * full 3x3 links (0, the default): the SU(3) reconstruction the paper's
- * single-precision solver uses (Sec. 2; it keeps two columns, here two rows).  An SU(3) matrix is fixed by its first two
- * rows (row 2 = conj(row0 x row1)), so the hopping and Schwarz kernels read
- * 48 (FP32) or 24 (FP16) bytes per link instead of 72 / 36 and rebuild the
- * third row in registers; FP64 work always uses the full links.  Enabling
+ * single-precision solver uses (Sec. 2; it keeps two columns, here two
+ * rows).  An SU(3) matrix is fixed by its first two rows (row 2 =
+ * conj(row0 x row1)), so the hopping and Schwarz kernels read 48 (FP32) or
+ * 24 (FP16) bytes per link instead of 72 / 36 and rebuild the third row in
+ * registers; FP64 work always uses the full links.  The context then holds
+ * the FP32 two-row links twice (field-major for the hopping kernels, per site
+ * for the Schwarz block solves: 384 bytes a site each) and the FP16 ones
+ * once.  Enabling
  * checks, on the current and every later wcl_set_gauge, that each link is
  * SU(3) to 1e-7 (row norms, row orthogonality, row 2 against the cross
  * product); otherwise the call fails with WCL_EINVAL and, in wcl_set_gauge,
