@@ -204,6 +204,9 @@ typedef struct {
                           * [nrhs][V][4][3] on the device (the paper's solver takes the
                           * solution vector in and out, Sec. 2); its even sites start
                           * the even/odd solvers, the whole field the full-D solver */
+    int ras_block[4];    /* Schwarz cores (with use_ras): all 0 keeps the context's
+                          * (the tiles, or wcl_set_ras_cores); else set as by
+                          * wcl_set_ras_cores for this and later solves           */
 } wcl_solve_opts;
 
 typedef struct {

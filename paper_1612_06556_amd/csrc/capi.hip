@@ -1594,7 +1594,10 @@ extern "C" int wcl_solve(wcl_ctx *c, const double *b, double *x, int nrhs, const
     const bool plain = o.outer == WCL_OUTER_PLAIN64;
     const bool plain_eo = o.outer == WCL_OUTER_PLAIN64_EO;
     const bool inner = !plain && !plain_eo;
-    if (o.use_ras && inner) CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver, o.ras_mult));
+    if (o.use_ras && inner) {
+        CHK(wcl_set_ras(c, o.ras_overlap, o.ras_iters, o.ras_solver, o.ras_mult));
+        if (o.ras_block[0] || o.ras_block[1] || o.ras_block[2] || o.ras_block[3]) CHK(wcl_set_ras_cores(c, o.ras_block));
+    }
     if (o.persistent && o.use_ras && (ras_generic(c) || c->ras_mult || c->ras_solver != WCL_RAS_MR))
         return fail(WCL_EINVAL, "the persistent inner solve runs the additive Schwarz with minimal-residual "
                                 "blocks of the fused kernel (tile cores, at most 648 sites per parity)");

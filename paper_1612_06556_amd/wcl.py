@@ -37,7 +37,7 @@ class wcl_solve_opts(ctypes.Structure):
                 ("ras_overlap", ctypes.c_int), ("ras_iters", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int), ("adjoint", ctypes.c_int),
                 ("ras_solver", ctypes.c_int), ("inner_vec_prec", ctypes.c_int), ("ras_mult", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("x0_dev", ctypes.c_void_p)]
+                ("persistent", ctypes.c_int), ("x0_dev", ctypes.c_void_p), ("ras_block", ctypes.c_int * 4)]
 
 
 class wcl_solve_info(ctypes.Structure):
@@ -341,6 +341,8 @@ class Lattice:
         for k, v in kw.items():
             if not hasattr(o, k) or k == "x0_dev":
                 raise KeyError(k)
+            if k == "ras_block":
+                v = (ctypes.c_int * 4)(*v)
             setattr(o, k, v)
         if x0 is not None:
             x0, n0 = self._spinors(x0)

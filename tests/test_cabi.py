@@ -38,7 +38,7 @@ def _struct_fields(name):
     src = open(os.path.join(ROOT, "include", "wcl.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
-    return [m.group(2) for m in re.finditer(r"\b(int|double|const double\s*\*)\s*([a-z_0-9]+)\s*;", body)]
+    return [m.group(2) for m in re.finditer(r"\b(int|double|const double\s*\*)\s*([a-z_0-9]+)\s*(\[\d+\])?\s*;", body)]
 
 
 @pytest.mark.parametrize("name", ["wcl_solve_opts", "wcl_solve_info", "wcl_kstat", "wcl_tuning"])

@@ -146,6 +146,34 @@ def test_solve_large_cores_batched():
     lat.close()
 
 
+def test_solve_opts_ras_block():
+    """opts.ras_block sets the Schwarz cores as wcl_set_ras_cores does: the
+    solve is bitwise that of the explicit call, reaches the oracle's x, the
+    cores stay for later solves, and bad cores are refused."""
+    from paper_1612_06556_amd import wcl
+    dims = (16, 8, 8, 16)
+    lat, orc = _lattice(dims, 1112, kappa=0.124)
+    b = synth.gaussian_spinor(dims, 1113)
+    x1, i1, rc1 = lat.solve(to_gpu(b), tol=1e-10, ras_block=(8, 4, 4, 8))
+    x2, i2, rc2 = lat.solve(to_gpu(b), tol=1e-10)            # the cores stay
+    lat.set_ras_cores(None)
+    x3, i3, rc3 = lat.solve(to_gpu(b), tol=1e-10)            # tile cores again
+    lat.set_ras_cores((8, 4, 4, 8))
+    x4, i4, rc4 = lat.solve(to_gpu(b), tol=1e-10)
+    print("ras_block", i1, i3, flush=True)
+    assert rc1 == rc2 == rc3 == rc4 == 0
+    assert np.array_equal(to_host(x1), to_host(x4)) and np.array_equal(to_host(x2), to_host(x4))
+    assert i1["inner_iters_total"] == i4["inner_iters_total"]
+    assert not np.array_equal(to_host(x1), to_host(x3))
+    xr, _ = orc.bicgstab_eo(b, 1e-13, 10000)
+    assert rel(to_host(x1), xr) <= 1e-8
+    for bad in ((3, 4, 4, 4), (16, 8, 8, 16)):   # odd; too large with overlap 1
+        with pytest.raises(wcl.WclError) as ei:
+            lat.solve(to_gpu(b), tol=1e-10, ras_block=bad)
+        assert ei.value.code == wcl.WCL_EINVAL
+    lat.close()
+
+
 def test_general_schwarz_refusals():
     from paper_1612_06556_amd import wcl
     dims = (8, 8, 8, 8)
