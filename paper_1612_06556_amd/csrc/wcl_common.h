@@ -421,6 +421,7 @@ template <typename S>
 WCL_D void load_link_raw_or_zero(__amdgpu_buffer_rsrc_t rs, int mu, int p, uint32_t h, bool in, uint32_t Vh,
                                  LinkRaw<S> &r)
 {
+    static_assert(sizeof(S) != 8, "FP64 links are not read through a 2 GiB resource");
     constexpr uint32_t OUT = 0x80000000u;
     const uint32_t mp = (uint32_t)(mu * 2 + p);
     const uint32_t o16 = in ? h * 16u : OUT, o8 = in ? h * 8u : OUT, o4 = in ? h * 4u : OUT;
@@ -432,9 +433,6 @@ WCL_D void load_link_raw_or_zero(__amdgpu_buffer_rsrc_t rs, int mu, int p, uint3
     } else if constexpr (std::is_same<S, R12h>::value) {
         r.v = ldb<uint4>(rs, mp * Vh * 16u + o16);
         r.w = ldb<uint2>(rs, 8u * Vh * 16u + mp * Vh * 8u + o8);
-    } else if constexpr (sizeof(S) == 8) {
-#pragma unroll
-        for (uint32_t i = 0; i < 9; i++) r.v[i] = ldb<double2>(rs, (mp * 9 + i) * Vh * 16u + o16);
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
         for (uint32_t k = 0; k < 4; k++) r.v[k] = ldb<float4>(rs, (mp * 4 + k) * Vh * 16u + o16);
