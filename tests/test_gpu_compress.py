@@ -67,6 +67,32 @@ def test_ras_compressed(prec):
     assert e <= (1e-5 if prec == 32 else 3e-3)
 
 
+def test_ras_compressed_new_gauge():
+    """A second wcl_set_gauge with two-row storage on rebuilds every copy the
+    Schwarz kernel reads (field-major and per-site two-row links): one RAS
+    application and one D application match the oracle of the new field, at
+    16^3x8 (several workgroups per XCD, cores on every tile face)."""
+    torch = require_gpu()
+    from paper_1612_06556_amd import wcl
+    dims = (16, 16, 16, 8)
+    lat, U1 = _lattice(dims, -1, 0.124, 1.0, 1201, None)
+    psi = synth.gaussian_spinor(dims, 1203)
+    psi[~even_mask(dims)] = 0
+    lat.set_ras(1, 4)
+    r1 = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=32))
+    U2 = synth.su3_field(dims, 1202)
+    lat.set_gauge(torch.from_numpy(U2).cuda())
+    lat.set_params(0.124, 1.0)
+    orc = oracle.Oracle(dims, -1, 0.124, 1.0, U2)
+    r2 = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=32))
+    e = rel(r2, orc.ras(psi, (4, 4, 4, 4), 1, 4))
+    ed = rel(to_host(lat.apply(to_gpu(psi), prec=32)), orc.D(psi))
+    print(f"RAS12 new gauge rel={e:.3e} D rel={ed:.3e}", flush=True)
+    assert e <= 1e-5 and ed <= TOL[32]
+    assert rel(r1, r2) > 1e-3   # the first field's result differs
+    lat.close()
+
+
 @pytest.mark.parametrize("use_ras,inner_prec", [(1, 32), (0, 16), (1, 16)])
 def test_solve_compressed(use_ras, inner_prec):
     dims = (8, 8, 8, 8)
