@@ -178,15 +178,22 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                 if not comp:
                     ms = _median_ms(lambda: lat.bench_clover(prec, 1000, copies))
                     clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
-    # single-use (cold) calls with non-temporal link and clover loads
+    # single-use (cold) calls with non-temporal link and clover loads, each tier
+    # with the launch shape the autotuner picks under that load policy
     lat.set_compression(0)
     tune = lat.autotune(32, 1, wcl.TUNE_HOP)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 1)
-    hop["fp32_cold_nontemporal"] = _rate(_median_ms(lambda: lat.bench_hop(32, 1000, 4)), Vh, 1320, 768)
-    lat.set_compression(1)
-    for prec in (32, 16):
+    nt_shapes = {}
+    for comp, prec in ((0, 32), (1, 32), (1, 16)):
+        lat.set_compression(comp)
+        t = lat.autotune(prec, 1, wcl.TUNE_HOP)
+        name = f"fp{prec}{'_r12' if comp else ''}_cold_nontemporal"
+        nt_shapes[name] = {k: t[k] for k in ("hop_block", "hop_depth", "hop_xcd", "hop_tiles")}
         ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
-        hop[f"fp{prec}_r12_cold_nontemporal"] = _rate(ms, Vh, 1320, 8 * (48 if prec == 32 else 24) + 192)
+        link_b = (48 if prec == 32 else 24) if comp else 72
+        hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
+    shapes["nontemporal"] = nt_shapes
+    lat.set_compression(1)
     wcl.wcl_set_tuning(lat.h, tune["hop_block"], tune["hop_depth"], tune["hop_xcd"], 0)
     # the same launch shape without the LDS staging of input spinors
     wcl.wcl_set_hop_staging(lat.h, 0)

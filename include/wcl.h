@@ -331,7 +331,9 @@ int wcl_set_hop_staging(wcl_ctx *ctx, int enable);
  * chosen launch shapes are set in the context; the Schwarz choice is
  * returned in *out (use_ras, ras_overlap) for the caller's opts.  Results
  * are cached per process, keyed by lattice, boundary condition, tiles,
- * precision, link storage, nrhs and flags (out->cached = 1 on a hit, the
+ * precision, link storage, nrhs, flags and the hop's load policy (non-temporal
+ * loads, LDS staging: candidates are timed with the context's current ones)
+ * (out->cached = 1 on a hit, the
  * shapes are then set without timing).  WCL_EINVAL for bad arguments. */
 enum { WCL_TUNE_HOP = 1, WCL_TUNE_BATCH = 2, WCL_TUNE_SCHWARZ = 4 };
 typedef struct {

@@ -1946,7 +1946,7 @@ extern "C" int wcl_set_batch_tuning(wcl_ctx *c, int rhs_per_thread)
 
 namespace {
 struct TuneKey {
-    int L[4], B[4], tbc, prec, compress, nrhs, flags, device;
+    int L[4], B[4], tbc, prec, compress, nrhs, flags, device, nt, stage;
     bool operator<(const TuneKey &o) const { return memcmp(this, &o, sizeof(TuneKey)) < 0; }
 };
 std::mutex g_tune_mu;
@@ -1967,6 +1967,8 @@ extern "C" int wcl_autotune(wcl_ctx *c, int prec, int nrhs, const double *b, con
     for (int mu = 0; mu < 4; mu++) { key.L[mu] = c->g.L[mu]; key.B[mu] = c->g.B[mu]; }
     key.tbc = c->g.tbc; key.prec = prec; key.compress = c->compress; key.nrhs = nrhs; key.flags = flags;
     key.device = c->device;
+    key.nt = c->hop_nt;              // candidates are timed with the caller's load policy
+    key.stage = c->hop_lds;
     wcl_tuning t;
     memset(&t, 0, sizeof(t));
     t.hop_block = c->hop_block; t.hop_depth = c->hop_depth; t.hop_xcd = c->hop_xcd; t.hop_tiles = c->hop_tpw;
