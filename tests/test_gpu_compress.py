@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import even_mask, rel, require_gpu, to_gpu, to_host
+from gpu_util import even_mask, rel, require_gpu, site_err, to_gpu, to_host
 from paper_1612_06556_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -163,6 +163,26 @@ def test_bench_shape_24x32_compressed():
         ms = lat.bench_hop(prec, 50, 4)
         print(f"hop12 prec={prec} cold {ms * 1e3:.2f} us", flush=True)
         assert ms > 0
+
+
+def test_ras_bench_shape_24x32():
+    """The benchmark's Schwarz application at full size (24^3x32, two-row
+    links, 1728 blocks, the per-site FP32 link copy): one application against
+    the oracle's, norm-wise and site by site."""
+    from paper_1612_06556_amd import wcl
+    dims = (24, 24, 24, 32)
+    lat, U = _lattice(dims, -1, 0.126, 1.0, 1003, None)
+    orc = oracle.Oracle(dims, -1, 0.126, 1.0, U)
+    psi = synth.gaussian_spinor(dims, 2004)
+    psi[~even_mask(dims)] = 0
+    lat.set_ras(1, 4)
+    ref = orc.ras(psi, (4, 4, 4, 4), 1, 4)
+    for prec, tol, stol in ((32, 1e-5, 1e-5), (16, 3e-3, 3e-3)):
+        out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=prec))
+        e, es = rel(out, ref), site_err(out, ref)
+        print(f"RAS12 24^3x32 prec={prec} rel={e:.3e} site={es:.3e}", flush=True)
+        assert e <= tol and es <= stol
+    lat.close()
 
 
 def test_long_lattice_24x96():
