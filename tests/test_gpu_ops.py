@@ -135,6 +135,11 @@ def test_ras_small_cores():
     out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=32))
     ref = orc.ras(psi, (2, 2, 2, 2), 1, 3)
     assert rel(out, ref) <= 1e-5
+    # two-row links (the per-site FP32 copy; FP16) on the small-block kernel
+    lat.set_compression(1)
+    for prec, tol in ((32, 1e-5), (16, 3e-3)):
+        out = to_host(lat.apply_op(wcl.OP_RAS, to_gpu(psi), prec=prec))
+        assert rel(out, ref) <= tol
 
 
 def test_multi_rhs_apply():
