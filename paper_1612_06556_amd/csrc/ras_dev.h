@@ -39,14 +39,14 @@ WCL_D void ext_to_global(const Geom &g, int mu, int b, int a, int delta, int &ti
 }
 
 // One hop of the block operator: the neighbour spinor comes from LDS, the
-// link from global memory (held encoded until the hop is computed); a
-// neighbour outside the extended block is replaced by the site itself with
-// weight 0 (Dirichlet cut without divergent branches).
+// link from global memory (held encoded until the hop is computed); a hop
+// that leaves the extended block reads a zero link and any valid LDS site
+// (Dirichlet cut without divergent branches).
 template <typename SL>
 struct RasStage {
     LinkRaw<SL> u;
     uint32_t ln;   // local half index of the neighbour (other parity)
-    float w;       // 0 (outside the block), else the t boundary sign
+    float w;       // the t boundary sign (t hops only)
 };
 
 WCL_D void ras_fence(cplx<float> acc[12], uint32_t &a, uint32_t &b)
