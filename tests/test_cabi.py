@@ -76,3 +76,52 @@ def test_create_refuses_fields_beyond_32bit_offsets():
     rc = lib.wcl_create(dims, -1, None, None, ctypes.byref(h))
     assert rc == wcl.WCL_EINVAL and not h.value
     assert b"too large" in lib.wcl_last_error()
+
+
+def test_every_call_refuses_a_null_context():
+    """Each exported call validates its context before touching the device:
+    a null context gives WCL_EINVAL and a message (wcl_destroy(NULL) is a
+    no-op returning WCL_OK); runs without a GPU."""
+    from paper_1612_06556_amd import wcl
+    lib = wcl.load()
+    n = None
+    d = ctypes.c_double()
+    i = ctypes.c_int()
+    st = wcl.wcl_kstat()
+    tu = wcl.wcl_tuning()
+    opts = wcl.wcl_default_opts()
+    info = (wcl.wcl_solve_info * 1)()
+    calls = {
+        "wcl_set_stream": lambda: lib.wcl_set_stream(n, n),
+        "wcl_set_gauge": lambda: lib.wcl_set_gauge(n, n),
+        "wcl_set_compression": lambda: lib.wcl_set_compression(n, 1),
+        "wcl_set_params": lambda: lib.wcl_set_params(n, 0.12, 1.0),
+        "wcl_set_ras": lambda: lib.wcl_set_ras(n, 1, 4, 0, 0),
+        "wcl_set_ras_cores": lambda: lib.wcl_set_ras_cores(n, n),
+        "wcl_apply": lambda: lib.wcl_apply(n, n, n, 1, 0, 32),
+        "wcl_apply_op": lambda: lib.wcl_apply_op(n, 0, n, n, 1, 32),
+        "wcl_apply_noalloc": lambda: lib.wcl_apply_noalloc(n, n, n, 1, 0, 32),
+        "wcl_solve": lambda: lib.wcl_solve(n, n, n, 1, ctypes.byref(opts), info),
+        "wcl_grad": lambda: lib.wcl_grad(n, n, n, n, ctypes.byref(d)),
+        "wcl_bench_hop": lambda: lib.wcl_bench_hop(n, 32, 1, 1, 1, ctypes.byref(d)),
+        "wcl_bench_clover": lambda: lib.wcl_bench_clover(n, 32, 1, 1, ctypes.byref(d)),
+        "wcl_bench_stream": lambda: lib.wcl_bench_stream(n, ctypes.c_double(1.0), 1, ctypes.byref(d), ctypes.byref(d)),
+        "wcl_profile": lambda: lib.wcl_profile(n, 1),
+        "wcl_profile_mask": lambda: lib.wcl_profile_mask(n, 1),
+        "wcl_profile_read": lambda: lib.wcl_profile_read(n, 0, ctypes.byref(st)),
+        "wcl_set_tuning": lambda: lib.wcl_set_tuning(n, 128, 2, 1, 0),
+        "wcl_set_hop_tiles": lambda: lib.wcl_set_hop_tiles(n, 1),
+        "wcl_set_hop_staging": lambda: lib.wcl_set_hop_staging(n, 1),
+        "wcl_set_batch_tuning": lambda: lib.wcl_set_batch_tuning(n, 1),
+        "wcl_autotune": lambda: lib.wcl_autotune(n, 32, 1, n, n, 1, ctypes.byref(tu)),
+        "wcl_autotune_hop": lambda: lib.wcl_autotune_hop(n, 32, 1, ctypes.byref(i)),
+    }
+    for name, call in calls.items():
+        rc = call()
+        assert rc == wcl.WCL_EINVAL, (name, rc)
+        assert lib.wcl_last_error(), name
+    assert lib.wcl_destroy(n) == wcl.WCL_OK
+    # every context-taking call of the header is exercised above
+    ctx_calls = [c for c in _declared() if c not in ("wcl_create", "wcl_destroy", "wcl_last_error",
+                                                    "wcl_default_opts")]
+    assert sorted(ctx_calls) == sorted(calls), sorted(set(ctx_calls) ^ set(calls))
