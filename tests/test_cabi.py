@@ -125,3 +125,27 @@ def test_every_call_refuses_a_null_context():
     ctx_calls = [c for c in _declared() if c not in ("wcl_create", "wcl_destroy", "wcl_last_error",
                                                     "wcl_default_opts")]
     assert sorted(ctx_calls) == sorted(calls), sorted(set(ctx_calls) ^ set(calls))
+
+
+def test_create_validates_before_allocating():
+    """wcl_create's argument checks (documented in the header) run before any
+    device call: odd or short extents, a bad boundary condition, tiles that
+    are odd or do not divide the lattice, and null pointers are refused."""
+    from paper_1612_06556_amd import wcl
+    lib = wcl.load()
+
+    def create(dims, tbc=-1, tile=None, out=True):
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int * 4)(*dims) if dims is not None else None
+        t = (ctypes.c_int * 4)(*tile) if tile is not None else None
+        rc = lib.wcl_create(d, tbc, t, None, ctypes.byref(h) if out else None)
+        assert not h.value
+        return rc
+
+    assert create((8, 8, 8, 7)) == wcl.WCL_EINVAL          # odd extent
+    assert create((8, 8, 8, 2)) == wcl.WCL_EINVAL          # extent below 4
+    assert create((8, 8, 8, 8), tbc=0) == wcl.WCL_EINVAL   # t_bc must be +1 or -1
+    assert create((8, 8, 8, 8), tile=(3, 2, 2, 2)) == wcl.WCL_EINVAL
+    assert create((8, 8, 8, 8), tile=(6, 2, 2, 2)) == wcl.WCL_EINVAL   # does not divide 8
+    assert create(None) == wcl.WCL_EINVAL
+    assert create((8, 8, 8, 8), out=False) == wcl.WCL_EINVAL
