@@ -76,6 +76,11 @@ def parse():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of known size "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--hop-only", action="store_true",
+                    help="run only the standalone hopping and clover kernels (no solve steps) and print "
+                         "their figures; for profiling those kernels on their own")
+    ap.add_argument("--hop-launches", type=int, default=1000,
+                    help="launches per timing trial of the standalone kernels")
     return ap.parse_args()
 
 
@@ -154,13 +159,12 @@ def _rate(ms, Vh, flop_site, bytes_site):
             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
-    """Standalone kernels (median of 5 trials of 1000 launches, cold = 4
-    rotating field sets beyond the 256 MB Infinity Cache, hot = 1 set; the
-    hops also cold with non-temporal link/clover loads), the device's streaming
-    ceilings, the paper's long lattice, and time-to-solution variants against
-    the plain FP64 solve."""
-    out = {}
+def hop_standalone(lat, Vh, wcl, launches=1000):
+    """The hopping kernel and the clover apply on their own (median of 5 trials
+    of `launches` launches, cold = 4 rotating field sets beyond the 256 MB
+    Infinity Cache, hot = 1 set; the hops also cold with non-temporal
+    link/clover loads, and without LDS staging), each storage tier with its own
+    autotuned launch shape. Leaves two-row links on and the FP32 shape tuned."""
     hop, clov = {}, {}
     shapes = {}
     for comp in (0, 1):
@@ -172,11 +176,11 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
             shapes[f"fp{prec}{'_r12' if comp else ''}"] = {k: t[k] for k in ("hop_block", "hop_depth", "hop_xcd",
                                                                            "hop_tiles")}
             for copies, tag in ((4, "cold"), (1, "hot")):
-                ms = _median_ms(lambda: lat.bench_hop(prec, 1000, copies))
+                ms = _median_ms(lambda: lat.bench_hop(prec, launches, copies))
                 name = f"fp{prec}{'_r12' if comp else ''}_{tag}"
                 hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
                 if not comp:
-                    ms = _median_ms(lambda: lat.bench_clover(prec, 1000, copies))
+                    ms = _median_ms(lambda: lat.bench_clover(prec, launches, copies))
                     clov[f"fp{prec}_{tag}"] = _rate(ms, Vh, 504, (288 if prec == 32 else 144) + 192)
     # single-use (cold) calls with non-temporal link and clover loads, each tier
     # with the launch shape the autotuner picks under that load policy
@@ -189,7 +193,7 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
         t = lat.autotune(prec, 1, wcl.TUNE_HOP)
         name = f"fp{prec}{'_r12' if comp else ''}_cold_nontemporal"
         nt_shapes[name] = {k: t[k] for k in ("hop_block", "hop_depth", "hop_xcd", "hop_tiles")}
-        ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
+        ms = _median_ms(lambda: lat.bench_hop(prec, launches, 4))
         link_b = (48 if prec == 32 else 24) if comp else 72
         hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
     shapes["nontemporal"] = nt_shapes
@@ -198,11 +202,20 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     # the same launch shape without the LDS staging of input spinors
     wcl.wcl_set_hop_staging(lat.h, 0)
     for prec in (32, 16):
-        ms = _median_ms(lambda: lat.bench_hop(prec, 1000, 4))
+        ms = _median_ms(lambda: lat.bench_hop(prec, launches, 4))
         hop[f"fp{prec}_r12_cold_unstaged"] = _rate(ms, Vh, 1320, 8 * (48 if prec == 32 else 24) + 192)
     wcl.wcl_set_hop_staging(lat.h, 1)
     lat.set_compression(1)
     lat.autotune(32, 1, wcl.TUNE_HOP)
+    return hop, shapes, clov
+
+
+def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
+    """Standalone kernels (`hop_standalone`), the device's streaming ceilings,
+    the paper's long lattice, and time-to-solution variants against the plain
+    FP64 solve."""
+    out = {}
+    hop, shapes, clov = hop_standalone(lat, Vh, wcl)
     out["hop_standalone"] = hop
     out["hop_standalone_shapes"] = shapes
     out["clover_standalone"] = clov
@@ -573,6 +586,12 @@ def main():
 
     # launch shape of the hopping kernel (project autotuner, untimed)
     tuning = lat.autotune(32, 1, wcl.TUNE_HOP)
+    if args.hop_only:
+        hop, shapes, clov = hop_standalone(lat, Vh, wcl, args.hop_launches)
+        print(json.dumps({"workload": "24x24x24x32 standalone kernels", "launches_per_trial": args.hop_launches,
+                          "hop_standalone": hop, "hop_standalone_shapes": shapes, "clover_standalone": clov}),
+              flush=True)
+        return
 
     # inner relative tolerance 0.1: the paper passes one without a value; the
     # sweep (--sweep) finds 0.1 the fastest of 1e-1 ... 1e-4 for this solve
