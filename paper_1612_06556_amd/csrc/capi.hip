@@ -578,11 +578,10 @@ constexpr double SU3_TOL = 1e-7;
 int build_compressed(wcl_ctx *c)
 {
     const size_t Vh = c->Vh;
-    if (!c->U32c) {
-        CHK(alloc(&c->U32c, link_bytes_c(P32C, Vh)));
-        CHK(alloc(&c->U16c, link_bytes_c(P16C, Vh)));
-        CHK(alloc(&c->U32s, link_bytes_c(P32C, Vh)));
-    }
+    // each copy on its own: a failed allocation leaves the others for the next call
+    if (!c->U32c) CHK(alloc(&c->U32c, link_bytes_c(P32C, Vh)));
+    if (!c->U16c) CHK(alloc(&c->U16c, link_bytes_c(P16C, Vh)));
+    if (!c->U32s) CHK(alloc(&c->U32s, link_bytes_c(P32C, Vh)));
     const int nb = 256;
     void *part;
     CHK(wsget(c, S_SU3, nb * sizeof(double), &part));
@@ -703,11 +702,10 @@ int wcl_set_gauge(wcl_ctx *c, const double *U)
 {
     if (!c || !U) return fail(WCL_EINVAL, "null argument");
     const size_t Vh = c->Vh;
-    if (!c->U64) {
-        CHK(alloc(&c->U64, link_bytes(8, Vh)));
-        CHK(alloc(&c->U32, link_bytes(4, Vh)));
-        CHK(alloc(&c->U16, link_bytes(2, Vh)));
-    }
+    // each field on its own: a failed allocation leaves the others for the next call
+    if (!c->U64) CHK(alloc(&c->U64, link_bytes(8, Vh)));
+    if (!c->U32) CHK(alloc(&c->U32, link_bytes(4, Vh)));
+    if (!c->U16) CHK(alloc(&c->U16, link_bytes(2, Vh)));
     HIPCHK(launch_ingest_gauge(c->g, U, c->U64, c->U32, c->U16, c->st));
     c->have_gauge = false;
     c->have_params = false;
@@ -738,14 +736,10 @@ int wcl_set_params(wcl_ctx *c, double kappa, double csw)
     if (!c->have_gauge) return fail(WCL_ESTATE, "wcl_set_params before wcl_set_gauge");
     if (!std::isfinite(kappa) || !std::isfinite(csw)) return fail(WCL_EINVAL, "kappa and csw must be finite");
     const size_t Vh = c->Vh;
-    if (!c->T64) {
-        CHK(alloc(&c->T64, clover_bytes(8, Vh)));
-        CHK(alloc(&c->Ti64, clover_bytes(8, Vh)));
-        CHK(alloc(&c->T32, clover_bytes(4, Vh)));
-        CHK(alloc(&c->Ti32, clover_bytes(4, Vh)));
-        CHK(alloc(&c->T16, clover_bytes(2, Vh)));
-        CHK(alloc(&c->Ti16, clover_bytes(2, Vh)));
-    }
+    void **cl[] = {&c->T64, &c->Ti64, &c->T32, &c->Ti32, &c->T16, &c->Ti16};
+    const int cl_bytes[] = {8, 8, 4, 4, 2, 2};
+    for (int i = 0; i < 6; ++i)
+        if (!*cl[i]) CHK(alloc(cl[i], clover_bytes(cl_bytes[i], Vh)));
     c->kappa = kappa;
     c->csw = csw;
     int zero = 0, bad = 0;
