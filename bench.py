@@ -43,7 +43,7 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 PMC_TRAFFIC = {
     "ras": {"fetch_kib": 1835288.4, "fetch_scale": 1048576 / 524315.3125, "write_kib": 82944.2,
             "write_scale": 1.0, "sources": ("ras.hip", "ras_dev.h", "wcl_common.h"),
-            "sha256": "2788171f54d1b40538f321b49774f12154a9cd7ef610f73f4cf3bdda69831b68",
+            "sha256": "8535dcf893e0b610a7013505d89cac67a031593bcd8b07d6ed6600594f3249a4",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 

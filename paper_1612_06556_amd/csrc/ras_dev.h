@@ -114,9 +114,9 @@ WCL_D void ras_compute(const RasStage<SL> &st, const float2 *src, cplx<float> ac
 
 // The first two link loads of a pass, then acc = 0.  The loads' fences take
 // the previous pass's accumulator, so they wait for the work that consumed
-// it.  (Issuing them before the barrier that ends the previous pass does not
-// pay: the barrier waits for every outstanding load, and the longer live
-// ranges spill.)
+// it.  (The workgroup barriers wait for LDS operations only, so loads issued
+// before the barrier that ends the previous pass would stay in flight across
+// it; that measured no faster, and the longer live ranges spill.)
 template <typename SL>
 WCL_D void ras_hop_start(const void *links, int q, const RasSite &S, uint32_t Vh, uint32_t t, const int *gnb,
                          RasStage<SL> &A, RasStage<SL> &B, cplx<float> acc[12])
