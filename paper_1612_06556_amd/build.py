@@ -13,6 +13,8 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions stay off (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every fused multiply-add is written in the source
+    "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
 

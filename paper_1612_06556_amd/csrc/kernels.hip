@@ -861,7 +861,11 @@ WCL_D float2 ldv(const float2 &v) { return v; }
 WCL_D float2 ldv(const __half2 &v) { return __half22float2(v); }
 WCL_D void stv(double2 &d, double x, double y) { d = make_double2(x, y); }
 WCL_D void stv(float2 &d, float x, float y) { d = make_float2(x, y); }
-WCL_D void stv(__half2 &d, float x, float y) { d = __floats2half2_rn(x, y); }
+WCL_D void stv(__half2 &d, float x, float y)
+{
+    fp32_as_computed(x, y);
+    d = __floats2half2_rn(x, y);
+}
 
 // partials[rhs][(2*k + {0,1}) * RED_BLOCKS + block] = (Re, Im) of sum conj(a_k) b_k
 // over the rhs-th slice (stride elements apart); blockIdx.y = rhs.

@@ -177,7 +177,11 @@ struct PVec {
 WCL_D float2 pld(const float2 &v) { return v; }
 WCL_D float2 pld(const __half2 &v) { return __half22float2(v); }
 WCL_D void pst(float2 &d, float x, float y) { d = make_float2(x, y); }
-WCL_D void pst(__half2 &d, float x, float y) { d = __floats2half2_rn(x, y); }
+WCL_D void pst(__half2 &d, float x, float y)
+{
+    fp32_as_computed(x, y);
+    d = __floats2half2_rn(x, y);
+}
 
 template <typename SV>
 WCL_D typename PVec<SV>::V *vec(void *base, int rhs, size_t stride)

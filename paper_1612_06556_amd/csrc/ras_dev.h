@@ -358,9 +358,9 @@ WCL_D void ras_block(const RasArgs &a, int blk, int rhs, RasLds<MAXNE> &L)
                 const float2 r = sE[c * MAXNE + t];
                 qv[c] = {fmaf(-a.kappa2, w[c].re, r.x), fmaf(-a.kappa2, w[c].im, r.y)};
                 if constexpr (!JAC) {
-                    qr += qv[c].re * r.x + qv[c].im * r.y;
-                    qi += qv[c].re * r.y - qv[c].im * r.x;
-                    qq += qv[c].re * qv[c].re + qv[c].im * qv[c].im;
+                    qr = fmaf(qv[c].re, r.x, fmaf(qv[c].im, r.y, qr));
+                    qi = fmaf(qv[c].re, r.y, fmaf(-qv[c].im, r.x, qi));
+                    qq = fmaf(qv[c].re, qv[c].re, fmaf(qv[c].im, qv[c].im, qq));
                 }
             }
             dots[0] = qr; dots[1] = qi; dots[2] = qq;
@@ -400,8 +400,9 @@ WCL_D void ras_block(const RasArgs &a, int blk, int rhs, RasLds<MAXNE> &L)
 #pragma unroll
             for (int c = 0; c < 12; c++) {
                 const float2 r = sE[c * MAXNE + t];
-                if (core) z[c] = {z[c].re + ar * r.x - ai * r.y, z[c].im + ar * r.y + ai * r.x};
-                sE[c * MAXNE + t] = make_float2(r.x - (ar * qv[c].re - ai * qv[c].im), r.y - (ar * qv[c].im + ai * qv[c].re));
+                if (core) z[c] = {fmaf(ar, r.x, fmaf(-ai, r.y, z[c].re)), fmaf(ar, r.y, fmaf(ai, r.x, z[c].im))};
+                sE[c * MAXNE + t] = make_float2(fmaf(-ar, qv[c].re, fmaf(ai, qv[c].im, r.x)),
+                                                fmaf(-ar, qv[c].im, fmaf(-ai, qv[c].re, r.y)));
             }
             if (core) store_spinor<SV, float>(rout, SE.g, Vh, z);
         }

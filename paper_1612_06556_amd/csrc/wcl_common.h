@@ -139,17 +139,21 @@ template <typename R> WCL_HD cplx<R> cmk(R a, R b) { return cplx<R>{a, b}; }
 template <typename R> WCL_HD cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename R> WCL_HD cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename R> WCL_HD cplx<R> operator-(cplx<R> a) { return {-a.re, -a.im}; }
+// Every fused multiply-add is written out (the library is built without
+// implicit contraction), so a kernel's rounding is what its source says,
+// whatever the surrounding code: variants of a kernel (staged or not, other
+// launch shapes) give bitwise equal results.
+WCL_HD float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+WCL_HD double fmar(double a, double b, double c) { return fma(a, b, c); }
 template <typename R> WCL_HD cplx<R> operator*(cplx<R> a, cplx<R> b)
 {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fmar(a.re, b.re, -(a.im * b.im)), fmar(a.re, b.im, a.im * b.re)};
 }
 template <typename R> WCL_HD cplx<R> operator*(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
 template <typename R> WCL_HD cplx<R> conjm(cplx<R> a, cplx<R> b)  // conj(a) * b
 {
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fmar(a.re, b.re, a.im * b.im), fmar(a.re, b.im, -(a.im * b.re))};
 }
-WCL_HD float fmar(float a, float b, float c) { return fmaf(a, b, c); }
-WCL_HD double fmar(double a, double b, double c) { return fma(a, b, c); }
 template <typename R> WCL_HD cplx<R> cfma(cplx<R> a, cplx<R> b, cplx<R> c)  // a*b + c
 {
     return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
@@ -237,8 +241,15 @@ WCL_D float2 h2f2(uint32_t u)
     __half2 h = *reinterpret_cast<__half2 *>(&u);
     return __half22float2(h);
 }
+// FP32 to FP16 (round to nearest even) of values rounded to FP32 first.  The
+// empty asm keeps the compiler from folding the multiply-add that produced a
+// value into the conversion (one rounding straight to FP16), which it does in
+// some code shapes and not in others: FP16 results would then depend on the
+// code around the store.
+WCL_D void fp32_as_computed(float &a, float &b) { asm("" : "+v"(a), "+v"(b)); }
 WCL_D uint32_t f22h(float a, float b)
 {
+    fp32_as_computed(a, b);
     __half2 h = __floats2half2_rn(a, b);
     return *reinterpret_cast<uint32_t *>(&h);
 }
@@ -344,9 +355,9 @@ template <typename R>
 WCL_D void su3_third_row(cplx<R> u[9])
 {
     // row 2 = conj(row 0 x row 1)
-    const cplx<R> c0 = u[1] * u[5] - u[2] * u[4];
-    const cplx<R> c1 = u[2] * u[3] - u[0] * u[5];
-    const cplx<R> c2 = u[0] * u[4] - u[1] * u[3];
+    const cplx<R> c0 = cfma(u[1], u[5], -(u[2] * u[4]));
+    const cplx<R> c1 = cfma(u[2], u[3], -(u[0] * u[5]));
+    const cplx<R> c2 = cfma(u[0], u[4], -(u[1] * u[3]));
     u[6] = {c0.re, -c0.im};
     u[7] = {c1.re, -c1.im};
     u[8] = {c2.re, -c2.im};
