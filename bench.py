@@ -41,9 +41,9 @@ PAPER_KNC_HOP_GFLOPS = 200.0
 # FETCH_SIZE counts L2 misses, Infinity-Cache hits included.  Valid only for
 # the kernel sources it was taken on (checked by hash; else traffic is null).
 PMC_TRAFFIC = {
-    "ras": {"fetch_kib": 1835288.4, "fetch_scale": 1048576 / 524315.3125, "write_kib": 82944.2,
+    "ras": {"fetch_kib": 1832045.5, "fetch_scale": 1048576 / 524315.3125, "write_kib": 82944.2,
             "write_scale": 1.0, "sources": ("ras.hip", "ras_dev.h", "wcl_common.h"),
-            "sha256": "8535dcf893e0b610a7013505d89cac67a031593bcd8b07d6ed6600594f3249a4",
+            "sha256": "451b8c81dd189e2d08915806a3d687afc92a4e449d49647534c8d3992b186fdd",
             "profile": "profiles/k_ras_R12f_24x24x24x32_pmc.md"},
 }
 
