@@ -210,6 +210,31 @@ def hop_standalone(lat, Vh, wcl, launches=1000):
     return hop, shapes, clov
 
 
+XROW_TILE = (24, 4, 8, 4)
+
+
+def hop_xrow_tiles(gU, Vh, wcl, launches=1000):
+    """Cold hops (4 rotating field sets, non-temporal operator loads,
+    autotuned shape) on the other layout the library offers for single-use
+    calls: tiles spanning whole x-rows (24x4x8x4), whose x hops never leave
+    the tile.  The Schwarz kernel needs 4^4 tiles, so the solver keeps those."""
+    xl = wcl.Lattice(DIMS, -1, XROW_TILE)
+    xl.set_gauge(gU)
+    xl.set_params(KAPPA, CSW)
+    hop, shapes = {}, {}
+    for comp, prec in ((0, 32), (1, 32), (1, 16)):
+        xl.set_compression(comp)
+        wcl.wcl_set_tuning(xl.h, 128, 2, 1, 1)
+        t = xl.autotune(prec, 1, wcl.TUNE_HOP)
+        name = f"fp{prec}{'_r12' if comp else ''}_cold_nontemporal"
+        shapes[name] = {k: t[k] for k in ("hop_block", "hop_depth", "hop_xcd", "hop_tiles")}
+        ms = _median_ms(lambda: xl.bench_hop(prec, launches, 4))
+        link_b = (48 if prec == 32 else 24) if comp else 72
+        hop[name] = _rate(ms, Vh, 1320, 8 * link_b + 192)
+    xl.close()
+    return hop, shapes
+
+
 def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     """Standalone kernels (`hop_standalone`), the device's streaming ceilings,
     the paper's long lattice, and time-to-solution variants against the plain
@@ -217,6 +242,10 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     out = {}
     hop, shapes, clov = hop_standalone(lat, Vh, wcl)
     out["hop_standalone"] = hop
+    gU = torch.from_numpy(U).cuda()
+    xh, xs = hop_xrow_tiles(gU, Vh, wcl)
+    out["hop_standalone_tile_24x4x8x4"] = xh
+    out["hop_standalone_tile_24x4x8x4_shapes"] = xs
     out["hop_standalone_shapes"] = shapes
     out["clover_standalone"] = clov
     # measured streaming ceilings of this device (library kernels, 2 GiB buffers)
@@ -240,6 +269,19 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
             long[f"fp{prec}{'_r12' if comp else ''}"] = _rate(ms, vl, 1320, 8 * link_b + 192)
     long_lat.close()
     out["hop_24x24x24x96"] = long
+    # the same with tiles spanning whole x-rows (every call on this lattice is cold)
+    long_lat = wcl.Lattice(dl, -1, (24, 4, 4, 8))
+    long_lat.set_gauge(torch.from_numpy(np.tile(U, (3, 1, 1, 1))).cuda())
+    longx = {}
+    for comp in (0, 1):
+        long_lat.set_compression(comp)
+        for prec in (32, 16):
+            link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
+            long_lat.autotune(prec, 1, wcl.TUNE_HOP)
+            ms = _median_ms(lambda: long_lat.bench_hop(prec, 200, 1))
+            longx[f"fp{prec}{'_r12' if comp else ''}"] = _rate(ms, vl, 1320, 8 * link_b + 192)
+    long_lat.close()
+    out["hop_24x24x24x96_tile_24x4x4x8"] = longx
     # time-to-solution variants (one warm run each, median of 3)
     sol = {}
     variants = (("mixed_ras_fp32", opts, 1),
@@ -588,8 +630,10 @@ def main():
     tuning = lat.autotune(32, 1, wcl.TUNE_HOP)
     if args.hop_only:
         hop, shapes, clov = hop_standalone(lat, Vh, wcl, args.hop_launches)
+        xh, xs = hop_xrow_tiles(gU, Vh, wcl, args.hop_launches)
         print(json.dumps({"workload": "24x24x24x32 standalone kernels", "launches_per_trial": args.hop_launches,
-                          "hop_standalone": hop, "hop_standalone_shapes": shapes, "clover_standalone": clov}),
+                          "hop_standalone": hop, "hop_standalone_shapes": shapes, "clover_standalone": clov,
+                          "hop_standalone_tile_24x4x8x4": xh, "hop_standalone_tile_24x4x8x4_shapes": xs}),
               flush=True)
         return
 
@@ -692,6 +736,9 @@ def main():
         out["hopping_fp32"] = {k: {"GFlop/s": hs[f"fp32_{k}"]["GFlop/s"], "HBM_GB/s": hs[f"fp32_{k}"]["GB/s"],
                                    "frac_hbm": hs[f"fp32_{k}"]["frac_hbm"], "us": hs[f"fp32_{k}"]["us"]}
                                for k in ("cold", "hot", "cold_nontemporal")}
+        xh = out["hop_standalone_tile_24x4x8x4"]["fp32_cold_nontemporal"]
+        out["hopping_fp32"]["cold_nontemporal_tile_24x4x8x4"] = {
+            "GFlop/s": xh["GFlop/s"], "HBM_GB/s": xh["GB/s"], "frac_hbm": xh["frac_hbm"], "us": xh["us"]}
         tts = out["time_to_solution"]
         out["vs_plain_fp64"] = {"step_solve_ms": round(solve_ms, 3), "plain_fp64_eo_ms": tts["plain_fp64_eo"]["ms"],
                                 "plain_fp64_full_ms": tts["plain_fp64"]["ms"],

@@ -18,11 +18,12 @@ CASES = [  # dims, tbc, kappa, csw, seed, tile
     ((4, 6, 8, 4), -1, 0.125, 1.3, 7, None),        # 2^4 tiles, Vh = 384: ragged workgroup
     ((6, 4, 4, 8), 1, 0.126, 1.0, 8, (2, 2, 2, 4)),  # periodic, non-cubic tile
     ((8, 8, 8, 16), -1, 0.126, 1.0, 9, (4, 4, 4, 4)),
+    ((8, 8, 8, 16), -1, 0.126, 1.0, 11, (8, 4, 8, 4)),  # tiles spanning whole x-rows (and z)
 ]
 
 
 def _ids(c):
-    return "x".join(map(str, c[0])) + f"_tbc{c[1]}"
+    return "x".join(map(str, c[0])) + f"_tbc{c[1]}" + ("_tile" + "x".join(map(str, c[5])) if c[5] else "")
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
@@ -252,6 +253,41 @@ def test_ras_zero_blocks(prec):
     assert e <= (1e-5 if prec == 32 else 3e-3)
     # cores at t = 8..11: their extended blocks (t = 7..12) miss the support
     assert np.abs(out[(x[:, 3] >= 8) & (x[:, 3] < 12)]).max() == 0.0
+
+
+def test_xrow_tiles_bench_layout():
+    """The layout the benchmark times its cold hops on besides 4^4 tiles:
+    24x4x8x4 tiles (whole x-rows) at 24^3x32.  H and D in FP32 and FP16,
+    full and two-row links, with the autotuned launch shape under temporal
+    and non-temporal loads, against the oracle (norm-wise and per site);
+    staged and unstaged give bitwise one result."""
+    from paper_1612_06556_amd import wcl
+    from gpu_util import site_err
+    dims = (24, 24, 24, 32)
+    lat, orc, _ = setup(dims, -1, 0.126, 1.0, 1003, (24, 4, 8, 4))
+    psi = synth.gaussian_spinor(dims, 2003)
+    g = to_gpu(psi)
+    ref_hop, ref_d = orc.hop(psi), orc.D(psi)
+    site_tol = {32: 1e-5, 16: 3e-2}   # 10x the norm-wise bound, as the launch-shape tests
+    for comp in (0, 1):
+        lat.set_compression(comp)
+        for prec in (32, 16):
+            for nt in (1, 0):
+                wcl.wcl_set_tuning(lat.h, 128, 2, 1, nt)
+                t = lat.autotune(prec, 1, wcl.TUNE_HOP)
+                hop = lat.apply_op(wcl.OP_HOP, g, prec=prec)
+                d = to_host(lat.apply(g, prec=prec))
+                wcl.wcl_set_hop_staging(lat.h, 0)
+                hop_u = lat.apply_op(wcl.OP_HOP, g, prec=prec)
+                wcl.wcl_set_hop_staging(lat.h, 1)
+                assert bool((hop == hop_u).all())
+                hop = to_host(hop)
+                e_h, e_d = rel(hop, ref_hop), rel(d, ref_d)
+                s_h = site_err(hop, ref_hop)
+                print(f"xrow tiles comp={comp} prec={prec} nt={nt} shape={t['hop_block']}/{t['hop_depth']}/"
+                      f"{t['hop_tiles']} hop rel={e_h:.3e} site={s_h:.3e} D rel={e_d:.3e}", flush=True)
+                assert e_h <= TOL[prec] and e_d <= TOL[prec] and s_h <= site_tol[prec]
+    wcl.wcl_set_tuning(lat.h, 256, 2, 1, 0)
 
 
 def test_hop_variants_bitwise_many_rhs():
