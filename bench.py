@@ -260,28 +260,31 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
     long_lat = wcl.Lattice(dl, -1)
     long_lat.set_gauge(torch.from_numpy(np.tile(U, (3, 1, 1, 1))).cuda())
     vl = int(np.prod(dl)) // 2
-    long = {}
-    for comp in (0, 1):
-        long_lat.set_compression(comp)
-        for prec in (32, 16):
-            link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
-            ms = _median_ms(lambda: long_lat.bench_hop(prec, 200, 1))
-            long[f"fp{prec}{'_r12' if comp else ''}"] = _rate(ms, vl, 1320, 8 * link_b + 192)
+    def long_hops(ll, nt_too):
+        """One field set (this lattice's links alone exceed the Infinity Cache),
+        autotuned shape, temporal and non-temporal operator loads."""
+        res = {}
+        for comp in (0, 1):
+            ll.set_compression(comp)
+            for prec in (32, 16):
+                link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
+                for nt in ((0, 1) if nt_too else (0,)):
+                    # the launch shape tuned under this load policy (the autotuner keeps it)
+                    wcl.wcl_set_tuning(ll.h, 128, 2, 1, nt)
+                    ll.autotune(prec, 1, wcl.TUNE_HOP)
+                    ms = _median_ms(lambda: ll.bench_hop(prec, 200, 1))
+                    res[f"fp{prec}{'_r12' if comp else ''}{'_nontemporal' if nt else ''}"] = \
+                        _rate(ms, vl, 1320, 8 * link_b + 192)
+        wcl.wcl_set_tuning(ll.h, 128, 2, 1, 0)
+        return res
+
+    out["hop_24x24x24x96"] = long_hops(long_lat, True)
     long_lat.close()
-    out["hop_24x24x24x96"] = long
     # the same with tiles spanning whole x-rows (every call on this lattice is cold)
     long_lat = wcl.Lattice(dl, -1, (24, 4, 4, 8))
     long_lat.set_gauge(torch.from_numpy(np.tile(U, (3, 1, 1, 1))).cuda())
-    longx = {}
-    for comp in (0, 1):
-        long_lat.set_compression(comp)
-        for prec in (32, 16):
-            link_b = (48 if prec == 32 else 24) if comp else (72 if prec == 32 else 36)
-            long_lat.autotune(prec, 1, wcl.TUNE_HOP)
-            ms = _median_ms(lambda: long_lat.bench_hop(prec, 200, 1))
-            longx[f"fp{prec}{'_r12' if comp else ''}"] = _rate(ms, vl, 1320, 8 * link_b + 192)
+    out["hop_24x24x24x96_tile_24x4x4x8"] = long_hops(long_lat, True)
     long_lat.close()
-    out["hop_24x24x24x96_tile_24x4x4x8"] = longx
     # time-to-solution variants (one warm run each, median of 3)
     sol = {}
     variants = (("mixed_ras_fp32", opts, 1),
