@@ -407,6 +407,14 @@ def batch12(opts, torch, synth, wcl):
         hopb[f"rhs_per_thread_{rpt}"] = r
     wcl.wcl_set_batch_tuning(lat.h, 1)
     out["hop_fp16_links_12rhs"] = hopb
+    # the same on tiles spanning whole x-rows (the Schwarz kernel needs 4^4 tiles)
+    xl = wcl.Lattice(dims, -1, (32, 4, 4, 4))
+    xl.set_gauge(U)
+    xl.set_params(KAPPA, CSW)
+    wcl.wcl_autotune_hop(xl.h, 16, 1)
+    ms = _median_ms(lambda: xl.bench_hop(16, 200, 1, nrhs=12))
+    out["hop_fp16_links_12rhs_tile_32x4x4x4"] = _rate(ms, vh, 12 * 1320, 2592)
+    xl.close()
     lat.set_compression(1)
     out["tuning"] = lat.autotune(16, 12, wcl.TUNE_HOP | wcl.TUNE_BATCH)
     t1 = time.perf_counter()
