@@ -213,3 +213,33 @@ def test_general_schwarz_graph_replay(opts):
         assert np.array_equal(to_host(x0), to_host(x1))
         assert [i["inner_iters_total"] for i in i0] == [i["inner_iters_total"] for i in i1]
     lat.close()
+
+
+def test_schwarz_on_xrow_tiles():
+    """On a layout whose tiles span whole x-rows (8x4x8x4 on 8^3x16) the tile
+    cores cannot be extended by the overlap (WCL_EINVAL); explicit 4^4 cores
+    run the device-memory block path: one RAS application against the
+    oracle's RAS of the same recipe, and the solve reaches the oracle's x."""
+    torch = require_gpu()
+    from paper_1612_06556_amd import wcl
+    dims = (8, 8, 8, 16)
+    U = synth.su3_field(dims, 1120)
+    lat = wcl.Lattice(dims, -1, (8, 4, 8, 4))
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    lat.set_params(0.124, 1.0)
+    orc = oracle.Oracle(dims, -1, 0.124, 1.0, U)
+    b = synth.gaussian_spinor(dims, 1121)
+    with pytest.raises(wcl.WclError) as ei:
+        lat.solve(to_gpu(b), tol=1e-10)          # tile cores with overlap 1 exceed x
+    assert ei.value.code == wcl.WCL_EINVAL
+    lat.set_ras_cores((4, 4, 4, 4))
+    v = _even(dims, 1122)
+    for prec in (32, 16):
+        e = rel(_ras(lat, v, prec), orc.ras(v, (4, 4, 4, 4), 1, 4, 0))
+        print(f"xrow tiles RAS prec={prec} rel={e:.3e}", flush=True)
+        assert e <= TOL[prec]
+    x, info, rc = lat.solve(to_gpu(b), tol=1e-10)
+    xr, _ = orc.bicgstab_eo(b, 1e-13, 10000)
+    print("xrow tiles solve", info, flush=True)
+    assert rc == 0 and rel(to_host(x), xr) <= 1e-8
+    lat.close()
