@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the ablation solves")
     ap.add_argument("--sweep", action="store_true",
-                    help="add the solver sweeps: lattice size, Schwarz variants, inner tolerance, 12-RHS batch")
+                    help="add the solver sweeps: lattice size with more solvers, the 12-RHS batch with more "
+                         "variants (and the Schwarz / inner-tolerance variants when --no-extras skips them)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of known size "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -329,6 +330,7 @@ def extras(lat, U, gb, opts, Vh, torch, synth, wcl):
                                 "candidates": "the step's recipe (overlap 1), overlap 0, no Schwarz"}
     out["batch12_32x32x32x64"] = batch12(opts, torch, synth, wcl)
     out["lattice_sweep"] = lattice_sweep(opts, torch, synth, wcl)
+    out.update(schwarz_variants(opts, torch, synth, wcl))
     out["differentiation_16x16x16x32"] = backward_timing(torch, synth, wcl)
     # setup: gauge ingest + casts + SU(3) check + two-row copies, then clover build and inversion
     gU = torch.from_numpy(U).cuda()
@@ -498,35 +500,11 @@ def _timed_solve(lat, b, torch, runs=3, **kw):
             "outer": info["outer_iters"], "inner": info["inner_iters_total"], "true_relres": info["true_relres"]}
 
 
-def sweep(opts, torch, synth, wcl):
-    """Solver performance against lattice size, Schwarz and inner-tolerance
-    variants at 24^3x32, and the 12-point-source batch at 32^3x64."""
+def schwarz_variants(opts, torch, synth, wcl):
+    """The Schwarz and solver variants of the benchmark's system (24^3x32):
+    block solver, overlap, steps, cores, multiplicative scheme, defect
+    correction, no Schwarz; and the inner tolerance 1e-1 .. 1e-4."""
     out = {}
-    sizes = {}
-    for dims, kappa, seed in (((8, 8, 8, 8), 0.12, 1001), ((16, 16, 16, 32), 0.125, 1002),
-                              ((24, 24, 24, 32), 0.126, 1003), ((32, 32, 32, 64), 0.126, 1004)):
-        U = torch.from_numpy(synth.su3_field(dims, seed)).cuda()
-        b = torch.from_numpy(synth.gaussian_spinor(dims, seed + 1000)).cuda()
-        lat = wcl.Lattice(dims, -1)
-        lat.set_compression(1)
-        lat.set_gauge(U)
-        lat.set_params(kappa, CSW)
-        wcl.wcl_autotune_hop(lat.h, 32, 2)
-        vh = int(np.prod(dims)) // 2
-        ms = _median_ms(lambda: lat.bench_hop(32, 100, 4))
-        row = {"kappa": kappa, "hop_fp32_r12_cold": _rate(ms, vh, 1320, 8 * 48 + 192)}
-        for name, kw in (("mixed_ras_fp32", dict(opts, outer=wcl.OUTER_FBICGSTAB)),
-                         ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
-                         ("mixed_noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16)),
-                         ("plain_fp64_eo", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64_EO, max_outer=20000)),
-                         ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):
-            row[name] = _timed_solve(lat, b, torch, **kw)
-        sizes["x".join(map(str, dims))] = row
-        print(f"sweep: lattice {dims} done", file=sys.stderr, flush=True)
-        lat.close()
-        del U, b
-    out["lattice_size"] = sizes
-
     dims = (24, 24, 24, 32)
     U = torch.from_numpy(synth.su3_field(dims, 1003)).cuda()
     b = torch.from_numpy(synth.gaussian_spinor(dims, 2003)).cuda()
@@ -559,16 +537,51 @@ def sweep(opts, torch, synth, wcl):
         schwarz[name] = _timed_solve(lat, b, torch, **dict(opts, **kw))
     lat.set_ras_cores(None)
     out["schwarz_24x24x24x32"] = schwarz
-    print("sweep: Schwarz variants done", file=sys.stderr, flush=True)
+    print("Schwarz variants done", file=sys.stderr, flush=True)
     stol = {}
     for tol in (1e-1, 1e-2, 1e-3, 1e-4):
         stol[f"{tol:g}"] = {"ras_fp32": _timed_solve(lat, b, torch, **dict(opts, inner_tol=tol)),
                            "noras_fp16": _timed_solve(lat, b, torch, **dict(opts, inner_tol=tol, use_ras=0,
                                                                               inner_prec=16))}
     out["inner_tol_24x24x24x32"] = stol
-    print("sweep: inner tolerance done", file=sys.stderr, flush=True)
+    print("inner tolerance sweep done", file=sys.stderr, flush=True)
     lat.close()
     del U, b
+
+    return out
+
+
+def sweep(opts, torch, synth, wcl, variants=True):
+    """Solver performance against lattice size, Schwarz and inner-tolerance
+    variants at 24^3x32, and the 12-point-source batch at 32^3x64."""
+    out = {}
+    sizes = {}
+    for dims, kappa, seed in (((8, 8, 8, 8), 0.12, 1001), ((16, 16, 16, 32), 0.125, 1002),
+                              ((24, 24, 24, 32), 0.126, 1003), ((32, 32, 32, 64), 0.126, 1004)):
+        U = torch.from_numpy(synth.su3_field(dims, seed)).cuda()
+        b = torch.from_numpy(synth.gaussian_spinor(dims, seed + 1000)).cuda()
+        lat = wcl.Lattice(dims, -1)
+        lat.set_compression(1)
+        lat.set_gauge(U)
+        lat.set_params(kappa, CSW)
+        wcl.wcl_autotune_hop(lat.h, 32, 2)
+        vh = int(np.prod(dims)) // 2
+        ms = _median_ms(lambda: lat.bench_hop(32, 100, 4))
+        row = {"kappa": kappa, "hop_fp32_r12_cold": _rate(ms, vh, 1320, 8 * 48 + 192)}
+        for name, kw in (("mixed_ras_fp32", dict(opts, outer=wcl.OUTER_FBICGSTAB)),
+                         ("mixed_noras_fp16", dict(opts, use_ras=0, inner_prec=16)),
+                         ("mixed_noras_fp16_vec16", dict(opts, use_ras=0, inner_prec=16, inner_vec_prec=16)),
+                         ("plain_fp64_eo", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64_EO, max_outer=20000)),
+                         ("plain_fp64", dict(tol=1e-10, outer=wcl.OUTER_PLAIN64, max_outer=20000))):
+            row[name] = _timed_solve(lat, b, torch, **kw)
+        sizes["x".join(map(str, dims))] = row
+        print(f"sweep: lattice {dims} done", file=sys.stderr, flush=True)
+        lat.close()
+        del U, b
+    out["lattice_size"] = sizes
+
+    if variants:   # the default run (extras) measures them already
+        out.update(schwarz_variants(opts, torch, synth, wcl))
 
     # 12 point sources (spin x colour at the origin) at 32^3x64
     dims = (32, 32, 32, 64)
@@ -758,7 +771,7 @@ def main():
                                 "fastest_variant": min(tts, key=lambda k: tts[k]["ms"])}
 
     if args.sweep:
-        out["sweep"] = sweep(opts, torch, synth, wcl)
+        out["sweep"] = sweep(opts, torch, synth, wcl, variants=args.no_extras)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U, b)
     print(json.dumps(out), flush=True)
