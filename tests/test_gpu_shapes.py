@@ -24,6 +24,7 @@ CASES = [  # dims, tbc, kappa, csw, seed, tile
     ((8, 8, 8, 8), -1, 0.12, 1.0, 1001, None),
     ((4, 6, 8, 4), -1, 0.125, 1.3, 7, None),          # 2^4 tiles, ragged last workgroup
     ((24, 24, 24, 32), -1, 0.126, 1.0, 1003, None),   # the benchmark's lattice
+    ((8, 8, 8, 16), -1, 0.126, 1.0, 1005, (8, 4, 8, 4)),  # tiles spanning whole x-rows
 ]
 # block, depth, xcd, nt, stage, site blocks per workgroup
 SHAPES = [s + (1,) for s in itertools.product((64, 128, 256), (2, 3), (0, 1), (0, 1), (1, 0))]
@@ -33,7 +34,7 @@ _refs = {}
 
 
 def _reference(case, orc, psi, pe):
-    key = case[0]
+    key = (case[0], case[4])
     if key not in _refs:
         _refs.clear()
         _refs[key] = (orc.D(psi), orc.hop(psi), orc.schur(pe))
