@@ -947,13 +947,24 @@ __global__ void __launch_bounds__(512) k_finalize(int step, int nterms, const do
     const double *partials = partials_all + (size_t)rhs * 6 * pstride;
     if (sc->done && (step == BICG_ALPHA || step == BICG_OMEGA || step == BICG_RHO)) return;
     __shared__ double lds[6 * 16];
-    double v[6];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // each thread adds partials j = tid, tid + 512, ... in that order; eight of
+    // them per term are loaded before any is added, so the loads overlap
+    constexpr int U = 8;
+    for (int j0 = threadIdx.x; j0 < nparts; j0 += U * blockDim.x) {
+        double p[6][U];
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-        double t = 0.0;
-        if (k < nterms)
-            for (int j = threadIdx.x; j < nparts; j += blockDim.x) t += partials[k * pstride + j];
-        v[k] = t;
+        for (int k = 0; k < 6; k++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = j0 + u * (int)blockDim.x;
+                p[k][u] = (k < nterms && j < nparts) ? partials[k * pstride + j] : 0.0;
+            }
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (k < nterms && j0 + u * (int)blockDim.x < nparts) v[k] += p[k][u];
     }
     block_sum<6>(v, lds);
     if (threadIdx.x != 0) return;
