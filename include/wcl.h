@@ -65,7 +65,10 @@ enum { WCL_PREC64 = 64, WCL_PREC32 = 32, WCL_PREC16 = 16 };
  * calls, Sec. 2; here that state is explicit and owned by the context).
  * tile: extents of the internal blocked layout and of the Schwarz cores
  * (each even and dividing dims[mu]); NULL picks 4^4 when it divides the
- * lattice, else 2^4.  t_bc = +1 periodic, -1 antiperiodic in time.
+ * lattice, else 2^4.  Not in the paper (layout): 4^4 suits the fused
+ * Schwarz kernel and repeated (cache-resident) hops; tiles spanning whole
+ * x-rows (e.g. 24x4x8x4 on 24^3x32) make single-use hops faster, and a
+ * Schwarz solve on them needs explicit cores (wcl_set_ras_cores).  t_bc = +1 periodic, -1 antiperiodic in time.
  * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
  * context, owned by the caller until wcl_destroy.  Errors: WCL_EINVAL
  * (also for more than 7,456,540 sites: fields are addressed with 32-bit byte
